@@ -1,0 +1,118 @@
+"""Pins for the oracle's heat-kernel application p_K(L, t) x.
+
+Checked against: dense eigendecomposition (Sec. "Heat Diffusion on a Graph",
+H_t = Psi exp(-t Lambda) Psi^T), scipy's expm_multiply, FFT diagonalisation of
+the cycle and the torus, the complete graph's two-point spectrum, and the
+invariants symmetry, near-positivity, mass (L 1 = 0) and permutation
+equivariance.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.linalg import expm_multiply
+
+import synth
+from oracle import closed_forms, graph, heat, spectrum
+
+
+def small_knn(n=150, k=6, seed=3):
+    X = np.random.default_rng(seed).standard_normal((n, 4))
+    A, _ = graph.knn_graph(X, k)
+    return A, graph.laplacian(A)
+
+
+def csr(arrs, n):
+    return graph.csr_from_arrays(n, *arrs)
+
+
+@pytest.mark.parametrize("t,K", [(0.5, 10), (1.0, 20), (2.0, 30), (8.0, 30)])
+def test_apply_matches_eigendecomposition(t, K):
+    A, L = small_knn()
+    lam = 1.01 * spectrum.lambda_max(L)
+    x = np.random.default_rng(0).standard_normal((L.shape[0], 3))
+    exact = heat.heat_dense_exact(L, lam, t) @ x
+    got = heat.heat_apply(L, lam, t, K, x)
+    tail = heat.tail_bound(t, K)
+    assert np.linalg.norm(got - exact, axis=0).max() <= tail * np.linalg.norm(x, axis=0).max() + 1e-12
+
+
+def test_apply_matches_expm_multiply():
+    A, L = small_knn(n=200, k=8, seed=5)
+    lam = 1.05 * spectrum.lambda_max(L)
+    t, K = 2.0, 40
+    x = np.random.default_rng(1).standard_normal(L.shape[0])
+    ref = expm_multiply(-t * (2.0 / lam) * L, x)
+    np.testing.assert_allclose(heat.heat_apply(L, lam, t, K, x), ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [64, 257])
+def test_cycle_fft_closed_form(n):
+    L = graph.laplacian(csr(synth.cycle_graph(n), n))
+    t, K, lam = 2.0, 30, 4.0
+    x = np.random.default_rng(n).standard_normal((n, 2))
+    np.testing.assert_allclose(heat.heat_apply(L, lam, t, K, x),
+                               closed_forms.cycle_heat_apply(n, lam, t, K, x), atol=1e-13)
+
+
+def test_torus_fft_closed_form():
+    n1, n2 = 8, 13
+    n = n1 * n2
+    L = graph.laplacian(csr(synth.torus_graph(n1, n2), n))
+    t, K, lam = 1.0, 25, 8.0
+    x = np.random.default_rng(2).standard_normal(n)
+    np.testing.assert_allclose(heat.heat_apply(L, lam, t, K, x),
+                               closed_forms.torus_heat_apply(n1, n2, lam, t, K, x), atol=1e-13)
+
+
+def test_complete_graph_closed_form():
+    n = 30
+    L = graph.laplacian(csr(synth.complete_graph(n), n))
+    t, K = 1.3, 25
+    x = np.random.default_rng(3).standard_normal((n, 2))
+    np.testing.assert_allclose(heat.heat_apply(L, float(n), t, K, x),
+                               closed_forms.complete_heat_apply(n, t, K, x), atol=1e-13)
+    # limit form: e^{-2t} x + (1 - e^{-2t}) mean(x)
+    lim = np.exp(-2 * t) * x + (1 - np.exp(-2 * t)) * x.mean(axis=0, keepdims=True)
+    np.testing.assert_allclose(heat.heat_apply(L, float(n), t, K, x), lim, atol=1e-12)
+
+
+def test_symmetry_positivity_mass_permutation():
+    A, L = small_knn(n=120, k=5, seed=9)
+    n = L.shape[0]
+    lam = 1.01 * spectrum.lambda_max(L)
+    t, K = 2.0, 30
+    P = heat.heat_dense_poly(L, lam, t, K)
+    assert np.abs(P - P.T).max() < 1e-13
+    assert P.min() >= -heat.tail_bound(t, K) - 1e-14
+    b = heat.cheb_coeffs(t, K)
+    p0 = 0.5 * b[0] + np.sum(b[1:] * (-1.0) ** np.arange(1, K + 1))
+    x = np.random.default_rng(4).standard_normal(n)
+    assert abs(np.sum(heat.heat_apply(L, lam, t, K, x)) - p0 * np.sum(x)) < 1e-12
+    perm = np.random.default_rng(5).permutation(n)
+    Pm = sp.csr_matrix((np.ones(n), (np.arange(n), perm)), shape=(n, n))
+    Lp = (Pm @ L @ Pm.T).tocsr()
+    np.testing.assert_allclose(heat.heat_apply(Lp, lam, t, K, Pm @ x), Pm @ heat.heat_apply(L, lam, t, K, x),
+                               atol=1e-13)
+
+
+def test_time_derivative_matches_finite_difference():
+    A, L = small_knn(n=100, k=5, seed=11)
+    lam = 1.01 * spectrum.lambda_max(L)
+    t, K, h = 2.0, 40, 1e-5
+    x = np.random.default_rng(6).standard_normal(L.shape[0])
+    fd = (heat.heat_apply(L, lam, t + h, K, x) - heat.heat_apply(L, lam, t - h, K, x)) / (2 * h)
+    np.testing.assert_allclose(heat.heat_apply_dt(L, lam, t, K, x), fd, atol=1e-8)
+
+
+def test_underestimated_lambda_breaks_expansion():
+    """lam_hat far below lambda_max maps eigenvalues to y >> 1, where T_k grows
+    geometrically; the truncated series then misses the exact kernel by far more
+    than the tail bound (which only holds on [-1, 1])."""
+    A, L = small_knn(n=150, k=6, seed=13)
+    lmax = spectrum.lambda_max(L)
+    t, K = 2.0, 30
+    x = np.random.default_rng(7).standard_normal(L.shape[0])
+    good = heat.heat_apply(L, 1.01 * lmax, t, K, x) - heat.heat_dense_exact(L, 1.01 * lmax, t) @ x
+    bad = heat.heat_apply(L, 0.1 * lmax, t, K, x) - heat.heat_dense_exact(L, 0.1 * lmax, t) @ x
+    assert np.linalg.norm(good) < 1e-12
+    assert np.linalg.norm(bad) > 1e-3
