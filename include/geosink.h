@@ -1,0 +1,245 @@
+/*
+ * geosink.h -- C ABI of the MI355X (gfx950) Geodesic Sinkhorn hot path.
+ *
+ * Geodesic Sinkhorn (Huguet, Tong et al., "Geodesic Sinkhorn for Fast and
+ * Accurate Optimal Transport on Manifolds") computes entropic optimal transport
+ * between signals on a graph whose kernel is the graph heat kernel
+ * H_t = exp(-t L).  The kernel is never formed: every application is an
+ * order-K Chebyshev recurrence of sparse products with the graph Laplacian
+ * (Sec. "Chebyshev Polynomials"), and Algorithm 1 alternates two such
+ * applications per Sinkhorn iteration.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns a gs_status; GS_OK is 0, errors are negative.  No call
+ *    aborts, throws or prints.  gs_last_error() returns a thread-local message
+ *    describing the last failure on the calling thread.
+ *  - Argument validation happens before any HIP call; a call that fails
+ *    validation has no effect.
+ *  - Ownership: gs_graph and gs_plan handles are created and freed by the
+ *    library.  Every array argument is owned by the caller and only borrowed
+ *    for the duration of the call (device work reading or writing it is
+ *    enqueued on `stream` and may still be pending when the call returns,
+ *    unless the call returns host results, see below).
+ *  - Device signals are float32, node-major: an n x B block stores the B
+ *    values of node i contiguously at [i*B, i*B+B) (leading dimension B).
+ *  - Device work is enqueued on `stream` (0 = the null stream).  Calls that
+ *    write host outputs (distances, errors, counters, lambda_hat, gradients
+ *    in t) synchronise `stream` before returning.
+ *  - A gs_plan is not thread-safe: calls on one plan must not overlap (they
+ *    share the plan's device workspace).  Different plans are independent.
+ *  - Readings of the paper that the library fixes (all documented with the
+ *    oracle):  the operator is rescaled as L_op = (2/lambda_hat) L and t is
+ *    the diffusion time on L_op (H_t = exp(-t L_op), y = L_op - I); degree K
+ *    means coefficients b_0..b_K with b_0 halved (K sparse products); the
+ *    regularisation of Algorithm 1 is 4t; denominators are floored at phi.
+ */
+#ifndef GEOSINK_H
+#define GEOSINK_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+#define GS_MAX_K 256          /* largest Chebyshev degree a plan accepts */
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = -1,        /* bad argument (null pointer, size, value)   */
+    GS_ERR_OOM = -2,            /* device or host allocation failed           */
+    GS_ERR_HIP = -3,            /* a HIP runtime call failed                  */
+    GS_ERR_NOT_CONNECTED = -4,  /* graph has > 1 component and that was refused */
+    GS_ERR_SPECTRUM = -5,       /* lambda_max estimate could not be formed    */
+    GS_ERR_NONFINITE = -6,      /* non-finite value in an input or a result   */
+    GS_ERR_NO_DEVICE = -7       /* no usable gfx950 device                    */
+} gs_status;
+
+typedef struct gs_graph_s* gs_graph;
+typedef struct gs_plan_s* gs_plan;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* gs_last_error(void);
+
+/* GS_ABI_VERSION of the loaded library. */
+int32_t gs_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Common graph (Sec. "Geodesic Sinkhorn Distances": one affinity graph over  */
+/* all datasets; Sec. "Heat Diffusion on a Graph": A, D, L = D - A).          */
+/* ------------------------------------------------------------------------ */
+
+/* Build the symmetrised kNN graph of n points in R^d.
+ *   X      host float32 (n x d), row-major (point i at X[i*d .. i*d+d)).
+ *   k      neighbours per point, 1 <= k <= 32 and k < n.
+ *   require_connected  nonzero: return GS_ERR_NOT_CONNECTED (and no graph)
+ *          when the graph has more than one connected component.
+ * Edges are the union of the directed k-nearest-neighbour relations (self
+ * excluded, equal distances broken towards the lower node id); the weight of
+ * edge {i,j} is exp(-|x_i - x_j|^2 / m^2) with m the median of the n*k
+ * directed neighbour distances.  Candidate neighbours are found on the GPU
+ * (float32 Gram tiles, k+8 candidates per point) and ranked on the host in
+ * float64 by exact squared distance.  Device CSR (int32 row pointers and
+ * column ids, float32 weights) stays resident in the returned handle.
+ * Uses the current HIP device; work runs on `stream` and is complete when
+ * the call returns. */
+gs_status gs_graph_from_points(const float* X, int64_t n, int32_t d, int32_t k,
+                               int32_t require_connected, hipStream_t stream, gs_graph* out);
+
+/* Wrap a caller-built symmetric adjacency (host CSR arrays, copied).
+ *   rowptr int32 (n+1), col int32 (nnz), w float32 (nnz): A_ij = w for each
+ *   (i, col) entry.  Requirements (else GS_ERR_INVALID): rowptr[0] = 0,
+ *   non-decreasing, rowptr[n] = nnz < 2^31; col in [0, n); no self loops; no
+ *   duplicate entries in a row; w finite and >= 0; A symmetric in pattern
+ *   and bitwise in value.  Rows are stored sorted by column id. */
+gs_status gs_graph_from_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                            const float* w, hipStream_t stream, gs_graph* out);
+
+/* Scalars of a graph; any out pointer may be NULL.
+ *   edge_bound = max over edges of (d_i + d_j) >= lambda_max(L);
+ *   median_dist = m of the Gaussian weights (0 for gs_graph_from_csr). */
+gs_status gs_graph_info(gs_graph g, int64_t* n, int64_t* nnz, int32_t* n_components,
+                        double* deg_max, double* edge_bound, double* median_dist);
+
+/* Copy the graph to caller host arrays (any may be NULL): rowptr (n+1),
+ * col (nnz), w (nnz), deg (n; float32 of the float64 row sums of w). */
+gs_status gs_graph_export(gs_graph g, int32_t* rowptr, int32_t* col, float* w, float* deg);
+
+void gs_graph_destroy(gs_graph g);
+
+/* ------------------------------------------------------------------------ */
+/* Spectral rescaling and coefficients (Sec. "Chebyshev Polynomials")         */
+/* ------------------------------------------------------------------------ */
+
+/* Estimate lambda_hat >= lambda_max(L) for the rescaling L_op = (2/lambda_hat) L.
+ * Runs `iters` (>= 2) Lanczos steps on the GPU from a start vector drawn with
+ * `seed`, takes the largest Ritz value theta and returns
+ * min(safety * theta, edge_bound); safety >= 1.  The paper only assumes the
+ * spectrum is bounded; the bound check keeps the result valid when the
+ * safety factor is too generous.  Synchronises `stream`. */
+gs_status gs_lambda_max(gs_graph g, int32_t iters, uint64_t seed, double safety,
+                        hipStream_t stream, double* lambda_hat);
+
+/* Chebyshev coefficients of exp(-t(y+1)) on [-1,1]:
+ *   b[k] = 2 (-1)^k e^{-t} I_k(t), k = 0..K (b[0] NOT halved), and
+ *   db_dt[k] = d b[k] / dt (NULL to skip).  Host arrays of K+1 doubles.
+ * I_k is evaluated by Miller's backward recurrence normalised with
+ * e^t = I_0 + 2 sum_k I_k.  t >= 0, 0 <= K <= GS_MAX_K.  Pure host code. */
+gs_status gs_cheby_coeffs(double t, int32_t K, double* b, double* db_dt);
+
+/* sum_{k>K} |b_k|: bound on the truncation error of the degree-K series. */
+gs_status gs_cheby_tail_bound(double t, int32_t K, double* bound);
+
+/* ------------------------------------------------------------------------ */
+/* Plans: device workspace + tuned launch shape for (graph, K, B)            */
+/* ------------------------------------------------------------------------ */
+
+#define GS_PLAN_AUTOTUNE 1   /* time the candidate launch shapes at creation */
+#define GS_PLAN_NO_GRAPH 2   /* launch kernels directly instead of replaying  */
+                             /* captured hipGraphs                            */
+
+/* Create a plan for degree K (1..GS_MAX_K) and B (>= 1) right-hand sides.
+ * tune_cache: path of a JSON file caching autotuned shapes (NULL: no cache);
+ * read and updated only with GS_PLAN_AUTOTUNE.  Allocates device workspace
+ * (about 9*n*B floats, more on the first backward call). */
+gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const char* tune_cache,
+                         gs_plan* out);
+
+/* Override the launch shape of the fused Chebyshev step (tuning studies,
+ * tests).  vec = 1 (float lanes, only when B == 1) or 4 (float4 lanes);
+ * S lanes split each row's nonzeros (power of two), C lanes span column
+ * groups of vec floats (power of two), S*C <= 64, and the padded B must be a
+ * multiple of vec*C.  Cached hipGraphs of the plan are dropped. */
+gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C);
+
+/* Human-readable description of the chosen launch shape into buf. */
+gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len);
+
+void gs_plan_destroy(gs_plan p);
+
+/* ------------------------------------------------------------------------ */
+/* Hot path                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Y = p_K(L, t) X (Sec. "Chebyshev Polynomials"): b_0/2 X + sum_{k=1..K} b_k T_k(y) X
+ * with T_0 = X, T_1 = y X, T_k = 2 y T_{k-1} - T_{k-2}, y = (2/lambda_hat) L - I.
+ *   X, Y   device n x B.  Ydt: device n x B receiving (d/dt) p_K(L,t) X, or NULL.
+ *   lambda_hat > 0, t >= 0.  Y and X must not overlap. */
+gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, float* Y,
+                        float* Ydt, hipStream_t stream);
+
+/* Algorithm 1 (Geodesic Sinkhorn) for B independent pairs (column b of mu, nu).
+ *   a        device n vertex weights, or NULL for all ones.
+ *   mu, nu   device n x B, finite, >= 0 (not renormalised).
+ *   iters    J >= 1 Sinkhorn iterations, w^0 = 1, v updated before w.
+ *   phi      denominator floor (> 0, e.g. 1e-30): d = r if r > phi else phi.
+ *   ckpt_every, ckpt   if ckpt != NULL, w^{s*C} (C = ckpt_every >= 1) is
+ *            stored at ckpt + s*n*B for s = 0..ceil(J/C)-1 (device, caller
+ *            sized ceil(J/C)*n*B floats), for gs_sinkhorn_backward.
+ *   v, w     device n x B outputs v^J, w^J (either may be NULL).
+ *   dist     host B doubles: D = 4t sum_i a_i (mu_i ln v_i + nu_i ln w_i)
+ *            (0 ln 0 = 0), the value on Algorithm 1's return line; NULL ok.
+ *   marg_err host B doubles or NULL: ||a v p_K(a w) - a mu||_1 (one extra
+ *            heat application per call).
+ *   n_floored host int64 or NULL: count of floored denominators on the
+ *            numerators' supports over all iterations.
+ * Synchronises `stream` when any host output is requested. */
+gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, const float* mu,
+                      const float* nu, int32_t iters, float phi, int32_t ckpt_every, float* ckpt,
+                      float* v, float* w, double* dist, double* marg_err, int64_t* n_floored,
+                      hipStream_t stream);
+
+/* Gradient of sum_b grad_dist[b] * D_b with respect to mu, nu and t, through
+ * exactly `iters` unrolled iterations of Algorithm 1 (d floor(r)/dr = 1[r>phi],
+ * lambda_hat held fixed).  Iterates are recomputed segment by segment from
+ * the checkpoints written by gs_sinkhorn with the same arguments; p_K is
+ * symmetric, so every adjoint is another Chebyshev application, with a second
+ * accumulator (db_k/dt) for the gradient in t.
+ *   grad_dist  host B doubles (the upstream gradient of each D_b).
+ *   grad_mu, grad_nu  device n x B outputs (either may be NULL); entries off
+ *              the support of mu (resp. nu) are set to 0 (the derivative is
+ *              -infinity there).
+ *   grad_t     host B doubles or NULL (per-pair dD_b/dt times grad_dist[b]).
+ * Synchronises `stream` when grad_t is requested. */
+gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const float* a,
+                               const float* mu, const float* nu, int32_t iters, float phi,
+                               int32_t ckpt_every, const float* ckpt, const double* grad_dist,
+                               float* grad_mu, float* grad_nu, double* grad_t, hipStream_t stream);
+
+/* Fixed-support barycenter of the plan's B = m inputs (Sec. "Interpolation
+ * with discrete support"; the paper gives no algorithm: iterative Bregman
+ * projections, v_i = mu_i / p_K(a w_i), q_i = floor(p_K(a v_i)),
+ * p = exp(sum_i alpha_i ln q_i), w_i = p / q_i, from w_i = 1).
+ *   mus      device n x m inputs; alpha host m doubles (>= 0).
+ *   bary     device n output p.  v, w: device n x m outputs or NULL.
+ *   marg_err host m doubles or NULL: ||a v_i p_K(a w_i) - a mu_i||_1.
+ *   n_floored host int64 or NULL: floored denominators (on mu_i's support
+ *            for the v update, everywhere for q). */
+gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, const float* mus,
+                        const double* alpha, int32_t iters, float phi, float* bary, float* v,
+                        float* w, double* marg_err, int64_t* n_floored, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement helpers                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Average duration (ms, HIP events on `stream`) of `reps` launches of one
+ * fused Chebyshev step (k >= 2, update of T_k and the accumulator) in the
+ * plan's launch shape, and its algorithmic bytes per launch:
+ * 4(n+1) + 8 nnz + 20 n B (CSR once; gather T_{k-1} once; read T_{k-2};
+ * write T_k; read and write the accumulator).  Synchronises `stream`. */
+gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms,
+                            double* bytes_per_launch);
+
+/* dst[i] = src[i] for i < count (device float32) with a plain streaming copy
+ * kernel; a bandwidth reference for the step kernel. */
+gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEOSINK_H */

@@ -1,0 +1,25 @@
+"""Geodesic Sinkhorn on MI355X (gfx950): C-ABI library libgeosink.so + thin binding.
+
+The binding modules are loaded on first attribute access, so that the build
+script can run before the library exists; any use of the product path then
+fails loudly (ImportError) when libgeosink.so has not been built.
+"""
+from __future__ import annotations
+
+import importlib
+
+_API = ("Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "gs_abi_version",
+        "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs", "gs_cheby_tail_bound",
+        "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward", "gs_barycenter",
+        "gs_plan_time_step", "gs_stream_copy", "current_stream", "n_checkpoints")
+_AUTOGRAD = ("GeoSinkhornDistance", "geodesic_sinkhorn_distance")
+
+__all__ = list(_API + _AUTOGRAD)
+
+
+def __getattr__(name):
+    if name in _API:
+        return getattr(importlib.import_module(".api", __name__), name)
+    if name in _AUTOGRAD:
+        return getattr(importlib.import_module(".autograd", __name__), name)
+    raise AttributeError(name)

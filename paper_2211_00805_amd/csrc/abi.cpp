@@ -1,0 +1,282 @@
+// extern "C" entry points: argument validation (before any HIP call), error
+// capture into a thread-local message, and dispatch into the drivers.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+
+#include "plan.h"
+
+namespace gs {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+void fail(gs_status code, const std::string& msg) {
+    set_error(msg);
+    throw Fail{code};
+}
+
+namespace {
+
+template <class F>
+gs_status guarded(F&& f) {
+    clear_error();
+    try {
+        f();
+        return GS_OK;
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return GS_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return GS_ERR_INVALID;
+    } catch (...) {
+        set_error("unknown failure");
+        return GS_ERR_INVALID;
+    }
+}
+
+void require_device() {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        fail(GS_ERR_NO_DEVICE, "no HIP device is visible");
+    }
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    GS_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(GS_ERR_NO_DEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+}
+
+void check_plan_args(gs_plan p, double lam, double t) {
+    GS_REQUIRE(p != nullptr, "plan is NULL");
+    GS_REQUIRE(std::isfinite(lam) && lam > 0.0, "lambda_hat must be finite and > 0");
+    GS_REQUIRE(std::isfinite(t) && t >= 0.0, "t must be finite and >= 0");
+}
+
+}  // namespace
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
+
+gs_status gs_graph_from_points(const float* X, int64_t n, int32_t d, int32_t k, int32_t require_connected,
+                               hipStream_t stream, gs_graph* out) {
+    return guarded([&] {
+        GS_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        GS_REQUIRE(X != nullptr, "X is NULL");
+        GS_REQUIRE(n >= 2 && n < (int64_t)1 << 31, "n must be in [2, 2^31)");
+        GS_REQUIRE(d >= 1 && d <= 4096, "d must be in [1, 4096]");
+        GS_REQUIRE(k >= 1 && k <= 32 && k < n, "k must be in [1, 32] and < n");
+        for (int64_t i = 0; i < n * (int64_t)d; ++i)
+            if (!std::isfinite(X[i])) fail(GS_ERR_NONFINITE, "X holds a non-finite value");
+        require_device();
+        auto g = std::make_unique<gs_graph_s>();
+        build_graph_from_points(X, n, d, k, stream, *g);
+        if (require_connected && g->n_components != 1)
+            fail(GS_ERR_NOT_CONNECTED, "graph has " + std::to_string(g->n_components) + " connected components");
+        *out = g.release();
+    });
+}
+
+gs_status gs_graph_from_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col, const float* w,
+                            hipStream_t stream, gs_graph* out) {
+    return guarded([&] {
+        GS_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        GS_REQUIRE(n >= 1 && n < (int64_t)1 << 31, "n must be in [1, 2^31)");
+        GS_REQUIRE(nnz >= 0 && nnz < (int64_t)1 << 31, "nnz must be in [0, 2^31)");
+        GS_REQUIRE(rowptr != nullptr, "rowptr is NULL");
+        GS_REQUIRE(nnz == 0 || (col != nullptr && w != nullptr), "col / w is NULL");
+        auto g = std::make_unique<gs_graph_s>();
+        build_graph_from_csr(n, nnz, rowptr, col, w, *g);  // validates on the host
+        require_device();
+        upload_graph(*g, stream);
+        *out = g.release();
+    });
+}
+
+gs_status gs_graph_info(gs_graph g, int64_t* n, int64_t* nnz, int32_t* n_components, double* deg_max,
+                        double* edge_bound, double* median_dist) {
+    return guarded([&] {
+        GS_REQUIRE(g != nullptr, "graph is NULL");
+        if (n) *n = g->n;
+        if (nnz) *nnz = g->nnz;
+        if (n_components) *n_components = g->n_components;
+        if (deg_max) *deg_max = g->deg_max;
+        if (edge_bound) *edge_bound = g->edge_bound;
+        if (median_dist) *median_dist = g->median;
+    });
+}
+
+gs_status gs_graph_export(gs_graph g, int32_t* rowptr, int32_t* col, float* w, float* deg) {
+    return guarded([&] {
+        GS_REQUIRE(g != nullptr, "graph is NULL");
+        if (rowptr) std::memcpy(rowptr, g->h_rowptr.data(), (g->n + 1) * sizeof(int32_t));
+        if (col && g->nnz) std::memcpy(col, g->h_col.data(), g->nnz * sizeof(int32_t));
+        if (w && g->nnz) std::memcpy(w, g->h_val.data(), g->nnz * sizeof(float));
+        if (deg) std::memcpy(deg, g->h_deg.data(), g->n * sizeof(float));
+    });
+}
+
+void gs_graph_destroy(gs_graph g) { delete g; }
+
+gs_status gs_lambda_max(gs_graph g, int32_t iters, uint64_t seed, double safety, hipStream_t stream,
+                        double* lambda_hat) {
+    return guarded([&] {
+        GS_REQUIRE(g != nullptr, "graph is NULL");
+        GS_REQUIRE(lambda_hat != nullptr, "lambda_hat is NULL");
+        GS_REQUIRE(iters >= 2 && iters <= 10000, "iters must be in [2, 10000]");
+        GS_REQUIRE(std::isfinite(safety) && safety >= 1.0, "safety must be >= 1");
+        GS_REQUIRE(g->nnz > 0, "graph has no edges");
+        *lambda_hat = lambda_max(*g, iters, seed, safety, stream);
+    });
+}
+
+gs_status gs_cheby_coeffs(double t, int32_t K, double* b, double* db_dt) {
+    return guarded([&] {
+        GS_REQUIRE(b != nullptr, "b is NULL");
+        GS_REQUIRE(std::isfinite(t) && t >= 0.0, "t must be finite and >= 0");
+        GS_REQUIRE(K >= 0 && K <= GS_MAX_K, "K must be in [0, GS_MAX_K]");
+        cheby_coeffs(t, K, b, db_dt);
+    });
+}
+
+gs_status gs_cheby_tail_bound(double t, int32_t K, double* bound) {
+    return guarded([&] {
+        GS_REQUIRE(bound != nullptr, "bound is NULL");
+        GS_REQUIRE(std::isfinite(t) && t >= 0.0, "t must be finite and >= 0");
+        GS_REQUIRE(K >= 0 && K <= GS_MAX_K, "K must be in [0, GS_MAX_K]");
+        *bound = cheby_tail(t, K);
+    });
+}
+
+gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const char* tune_cache, gs_plan* out) {
+    return guarded([&] {
+        GS_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        GS_REQUIRE(g != nullptr, "graph is NULL");
+        GS_REQUIRE(K >= 1 && K <= GS_MAX_K, "K must be in [1, GS_MAX_K]");
+        GS_REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+        GS_REQUIRE((flags & ~(GS_PLAN_AUTOTUNE | GS_PLAN_NO_GRAPH)) == 0, "unknown plan flags");
+        require_device();
+        *out = plan_create(g, K, B, flags, tune_cache);
+    });
+}
+
+gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr, "plan is NULL");
+        const LaunchShape s{vec, S, C};
+        GS_REQUIRE(shape_supported(s), "unsupported launch shape");
+        GS_REQUIRE((vec == 1) == (p->ldp == 1), "vec must be 1 exactly when B == 1");
+        GS_REQUIRE(p->ldp % (vec * C) == 0, "padded B must be a multiple of vec*C");
+        GS_HIP(hipDeviceSynchronize());
+        drop_graphs(*p);
+        p->shape = s;
+        p->shape_origin = "set";
+    });
+}
+
+gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr && buf != nullptr && len > 0, "bad arguments");
+        const std::string s = "vec=" + std::to_string(p->shape.vec) + " S=" + std::to_string(p->shape.S) +
+                              " C=" + std::to_string(p->shape.C) + " ldp=" + std::to_string(p->ldp) +
+                              " origin=" + p->shape_origin + ((p->flags & GS_PLAN_NO_GRAPH) ? " graphs=off" : " graphs=on");
+        std::strncpy(buf, s.c_str(), len - 1);
+        buf[len - 1] = 0;
+    });
+}
+
+void gs_plan_destroy(gs_plan p) { delete p; }
+
+gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, float* Y, float* Ydt,
+                        hipStream_t stream) {
+    return guarded([&] {
+        check_plan_args(p, lambda_hat, t);
+        GS_REQUIRE(X != nullptr && Y != nullptr, "X / Y is NULL");
+        GS_REQUIRE(X != Y && (const float*)Ydt != X && Ydt != Y, "X, Y and Ydt must be distinct");
+        heat_apply(*p, lambda_hat, t, X, Y, Ydt, stream);
+    });
+}
+
+gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, const float* mu, const float* nu,
+                      int32_t iters, float phi, int32_t ckpt_every, float* ckpt, float* v, float* w, double* dist,
+                      double* marg_err, int64_t* n_floored, hipStream_t stream) {
+    return guarded([&] {
+        check_plan_args(p, lambda_hat, t);
+        GS_REQUIRE(mu != nullptr && nu != nullptr, "mu / nu is NULL");
+        GS_REQUIRE(iters >= 1, "iters must be >= 1");
+        GS_REQUIRE(std::isfinite(phi) && phi > 0.f, "phi must be finite and > 0");
+        GS_REQUIRE(ckpt == nullptr || ckpt_every >= 1, "ckpt_every must be >= 1 when ckpt is given");
+        sinkhorn(*p, lambda_hat, t, a, mu, nu, iters, phi, ckpt ? ckpt_every : 1, ckpt, v, w, dist, marg_err,
+                 n_floored, stream);
+    });
+}
+
+gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const float* a, const float* mu,
+                               const float* nu, int32_t iters, float phi, int32_t ckpt_every, const float* ckpt,
+                               const double* grad_dist, float* grad_mu, float* grad_nu, double* grad_t,
+                               hipStream_t stream) {
+    return guarded([&] {
+        check_plan_args(p, lambda_hat, t);
+        GS_REQUIRE(t > 0.0, "t must be > 0 for the backward");
+        GS_REQUIRE(mu != nullptr && nu != nullptr && ckpt != nullptr && grad_dist != nullptr,
+                   "mu / nu / ckpt / grad_dist is NULL");
+        GS_REQUIRE(iters >= 1 && ckpt_every >= 1, "iters and ckpt_every must be >= 1");
+        GS_REQUIRE(std::isfinite(phi) && phi > 0.f, "phi must be finite and > 0");
+        for (int b = 0; b < p->B; ++b) GS_REQUIRE(std::isfinite(grad_dist[b]), "grad_dist must be finite");
+        sinkhorn_backward(*p, lambda_hat, t, a, mu, nu, iters, phi, ckpt_every, ckpt, grad_dist, grad_mu, grad_nu,
+                          grad_t, stream);
+    });
+}
+
+gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, const float* mus,
+                        const double* alpha, int32_t iters, float phi, float* bary, float* v, float* w,
+                        double* marg_err, int64_t* n_floored, hipStream_t stream) {
+    return guarded([&] {
+        check_plan_args(p, lambda_hat, t);
+        GS_REQUIRE(mus != nullptr && alpha != nullptr && bary != nullptr, "mus / alpha / bary is NULL");
+        GS_REQUIRE(iters >= 1, "iters must be >= 1");
+        GS_REQUIRE(std::isfinite(phi) && phi > 0.f, "phi must be finite and > 0");
+        for (int i = 0; i < p->B; ++i) GS_REQUIRE(std::isfinite(alpha[i]) && alpha[i] >= 0.0, "alpha must be >= 0");
+        barycenter(*p, lambda_hat, t, a, mus, alpha, iters, phi, bary, v, w, marg_err, n_floored, stream);
+    });
+}
+
+gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms, double* bytes_per_launch) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr && avg_ms != nullptr, "plan / avg_ms is NULL");
+        GS_REQUIRE(reps >= 1, "reps must be >= 1");
+        *avg_ms = time_step(*p, p->shape, reps, stream);
+        if (bytes_per_launch)
+            *bytes_per_launch = 4.0 * (p->n + 1) + 8.0 * p->g->nnz + 20.0 * (double)p->n * p->B;
+    });
+}
+
+gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_t stream) {
+    return guarded([&] {
+        GS_REQUIRE(src != nullptr && dst != nullptr && count >= 0, "bad arguments");
+        launch_stream_copy(src, dst, count, stream);
+        GS_HIP(hipGetLastError());
+    });
+}
+
+}  // extern "C"

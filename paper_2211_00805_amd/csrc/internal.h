@@ -1,0 +1,184 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/geosink.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Fail {
+    gs_status code;
+};
+
+[[noreturn]] void fail(gs_status code, const std::string& msg);
+
+#define GS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            ::gs::fail(GS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GS_REQUIRE(cond, msg)                                  \
+    do {                                                       \
+        if (!(cond)) ::gs::fail(GS_ERR_INVALID, (msg));        \
+    } while (0)
+
+// Device allocation owned by RAII.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t count = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t c) { alloc(c); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t c) {
+        release();
+        if (c == 0) return;
+        void* q = nullptr;
+        if (hipMalloc(&q, c * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(GS_ERR_OOM, "hipMalloc of " + std::to_string(c * sizeof(T)) + " bytes failed");
+        }
+        p = static_cast<T*>(q);
+        count = c;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+};
+
+// ---------------------------------------------------------------- coefficients
+// e^{-t} I_k(t) for k = 0..kmax by Miller's backward recurrence.
+void bessel_ive_table(double t, int kmax, std::vector<double>& out);
+void cheby_coeffs(double t, int K, double* b, double* db);
+double cheby_tail(double t, int K);
+
+// ---------------------------------------------------------------- kernels (kernels.hip)
+enum StepFlags : int32_t {
+    STEP_FIRST = 1,      // k == 1: T_1 = y X, acc = b_0/2 X + b_1 T_1
+    STEP_WRITE_T = 2,    // store T_k
+    STEP_DUAL = 4,       // second accumulator with the d/dt coefficients
+    STEP_EPI_STORE = 8,  // write the accumulator (final or not)
+    STEP_EPI_SCALE = 16  // out = num / floor(acc); out_a = a * out; record floors
+};
+
+struct StepArgs {
+    const int32_t* rowptr;
+    const int32_t* col;
+    const float* val;
+    int32_t n;
+    int32_t ldp;          // leading dimension (padded B)
+    const float* tprev;   // T_{k-1} (T_0 = X when k == 1): gathered
+    const float* tprev2;  // T_{k-2} (k >= 2)
+    float* tout;          // T_k (may alias tprev2)
+    float* acc;
+    float* acc2;
+    const float* coef;    // [alpha, b_0..b_K, db_0..db_K] (float)
+    int32_t k;
+    int32_t K;
+    int32_t flags;
+    // scaling epilogue
+    const float* num;
+    float* out;
+    float* out_a;
+    const float* a;
+    float* rec;
+    float phi;
+    unsigned long long* nfloor;
+};
+
+struct LaunchShape {
+    int vec;   // 1 (float) or 4 (float4)
+    int S;     // lanes splitting a row's nonzeros
+    int C;     // lanes over column groups of `vec` floats
+    bool operator==(const LaunchShape& o) const { return vec == o.vec && S == o.S && C == o.C; }
+};
+
+bool shape_supported(const LaunchShape& s);
+std::vector<LaunchShape> candidate_shapes(int ldp);
+void launch_step(const LaunchShape& shape, const StepArgs& a, hipStream_t st);
+
+void launch_fill(float* p, float v, size_t count, hipStream_t st);
+void launch_copy_ld(const float* src, int lds, float* dst, int ldd, int64_t n, int B, hipStream_t st);
+void launch_set_coef(float* dcoef, double alpha, const double* b, const double* db, int K, hipStream_t st);
+void launch_stream_copy(const float* src, float* dst, int64_t count, hipStream_t st);
+
+// column reductions (fp64, deterministic two-pass)
+enum ReduceOp : int32_t {
+    RED_DIST = 0,   // sum a (mu ln v + nu ln w) over supports
+    RED_MARG = 1,   // sum |a v r - a mu|
+    RED_DOT = 2,    // sum a x y (y NULL: ones)
+    RED_DOT_QUOT = 3,  // sum a x0 x1 / x2
+};
+struct ReduceArgs {
+    int32_t op;
+    int64_t n;
+    int32_t ldp;
+    int32_t B;
+    const float* x0;   // DIST: mu   MARG: v   DOT: x   DOT_QUOT: x
+    const float* x1;   // DIST: v    MARG: r   DOT: y   DOT_QUOT: numerator
+    const float* x2;   // DIST: nu   MARG: mu           DOT_QUOT: denominator
+    const float* x3;   // DIST: w
+    const float* a;    // nullable
+};
+int reduce_blocks(int64_t n);
+void launch_reduce(const ReduceArgs& r, double* partials, int nblk, double* out, int accumulate,
+                   double scale_from, hipStream_t st);
+
+// barycenter row kernel: q = floor(acc); p = exp(sum alpha ln q); w = p / q; xw = a w
+void launch_bary_row(const float* acc, const float* alpha, int64_t n, int ldp, int m, float phi,
+                     float* bary, float* w, float* xw, const float* a, unsigned long long* nfloor,
+                     hipStream_t st);
+
+// backward elementwise kernels
+void launch_bwd_seed(const float* mu, const float* nu, const float* v, const float* w, const float* a,
+                     const float* g4t, int64_t n, int ldp, float* dmu, float* dnu, float* vbar_seed,
+                     float* wbar, hipStream_t st);
+void launch_bwd_e(const float* wbar, const float* e, const float* nu, int64_t n, int ldp, float phi,
+                  float* dnu, float* ebar, hipStream_t st);
+void launch_bwd_d(const float* z, float* vbar_seed, const float* d, const float* mu, const float* a,
+                  int64_t n, int ldp, float phi, float* dmu, float* dbar, hipStream_t st);
+void launch_bwd_w(const float* z, const float* a, int64_t n, int ldp, float* wbar, hipStream_t st);
+void launch_mul_a(const float* x, const float* a, int64_t n, int ldp, float* out, hipStream_t st);
+void launch_mask_support(const float* h, int64_t n, int ldp, float* g, hipStream_t st);
+
+// Laplacian mat-vec and Lanczos helpers (B = 1)
+void launch_lap_spmv(const int32_t* rowptr, const int32_t* col, const float* val, int32_t n,
+                     const float* x, float* y, hipStream_t st);
+void launch_lanczos_update(float* z, const float* q, const float* qprev, double alpha, double beta,
+                           int64_t n, hipStream_t st);
+void launch_scale(float* dst, const float* src, double s, int64_t n, hipStream_t st);
+
+// kNN candidates (knn.hip): cand (n x kk) int32, candidate ids sorted by fp32 Gram distance
+void launch_knn_candidates(const float* Xc, const float* norms, int64_t n, int d, int kk, int32_t* cand,
+                           hipStream_t st);
+void launch_row_norms(const float* Xc, int64_t n, int d, float* norms, hipStream_t st);
+
+}  // namespace gs
+
+// ---------------------------------------------------------------- handles
+struct gs_graph_s {
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int device = 0;
+    gs::DevBuf<int32_t> rowptr, col;
+    gs::DevBuf<float> val;
+    std::vector<int32_t> h_rowptr, h_col;
+    std::vector<float> h_val, h_deg;
+    int32_t n_components = 0;
+    double deg_max = 0.0, edge_bound = 0.0, median = 0.0;
+};

@@ -1,0 +1,572 @@
+// Device kernels of the Geodesic Sinkhorn hot path (gfx950, wave64).
+//
+// K1  cheb_step:   one Chebyshev step of p_K(L,t) X on n x B node-major signals,
+//                  T_k = 2 y T_{k-1} - T_{k-2}, acc += b_k T_k (Sec. "Chebyshev
+//                  Polynomials"), with y = (2/lambda_hat) L - I and
+//                  (L x)_i = sum_j A_ij (x_i - x_j) (Sec. "Heat Diffusion on a
+//                  Graph").  The sparse product, the three-term update and the
+//                  coefficient accumulate are one pass over HBM.
+// K2  epilogue of the last step: Algorithm 1's scaling out = num / floor(acc),
+//                  out_a = a * out (the next application's input), floors counted.
+// K3  colreduce:   per-column float64 reductions (distance, marginal error, dots)
+//                  in two deterministic passes, no floating-point atomics.
+// K4  bary_row:    barycenter update p = exp(sum alpha ln q), w = p / q.
+// K5  bwd_*:       elementwise adjoints of Algorithm 1's updates.
+//
+// The step kernel is bandwidth bound; its launch shape (lanes splitting a
+// row's nonzeros S, lanes across column groups C, float or float4 lanes) is
+// a template parameter chosen per plan, and the 1-D grid is remapped so that
+// each of the 8 XCDs (which receive blocks round-robin) walks a contiguous
+// range of rows, keeping the gathered rows of neighbouring nodes in that
+// XCD's L2.
+#include <cfloat>
+#include <cmath>
+
+#include "internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int nx = 8;
+    const int q = nb / nx, r = nb % nx;
+    const int x = b % nx, i = b / nx;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <int VEC>
+struct Vec {
+    float v[VEC];
+};
+
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> vload(const float* p) {
+    Vec<VEC> r;
+    if constexpr (VEC == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    } else {
+        r.v[0] = *p;
+    }
+    return r;
+}
+
+template <int VEC>
+__device__ __forceinline__ void vstore(float* p, const Vec<VEC>& r) {
+    if constexpr (VEC == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else {
+        *p = r.v[0];
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> vzero() {
+    Vec<VEC> r;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) r.v[i] = 0.f;
+    return r;
+}
+
+// sum += w * (own - x)
+template <int VEC>
+__device__ __forceinline__ void vacc(Vec<VEC>& sum, float w, const Vec<VEC>& own, const Vec<VEC>& x) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) sum.v[i] = fmaf(w, own.v[i] - x.v[i], sum.v[i]);
+}
+
+// ------------------------------------------------------------------ K1 + K2
+template <int VEC, int S, int C>
+__global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
+    constexpr int LPR = S * C;       // lanes per row
+    constexpr int RPW = 64 / LPR;    // rows per wave
+    constexpr int RPB = 4 * RPW;     // rows per block
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ldp = A.ldp;
+    const int ncoltiles = ldp / (VEC * C);
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int rt = L / ncoltiles;
+    const int ct = L - rt * ncoltiles;
+    const int lr = lane % LPR;
+    const int s = lr / C;
+    const int c = lr - s * C;
+    const int row = rt * RPB + wave * RPW + lane / LPR;
+    const bool valid = row < A.n;
+    const size_t off = (size_t)(valid ? row : 0) * ldp + ct * (VEC * C) + c * VEC;
+    const int colofs = ct * (VEC * C) + c * VEC;
+
+    Vec<VEC> own = vzero<VEC>();
+    Vec<VEC> sum = vzero<VEC>();
+    if (valid) {
+        own = vload<VEC>(A.tprev + off);
+        int e = A.rowptr[row] + s;
+        const int end = A.rowptr[row + 1];
+        for (; e + 3 * S < end; e += 4 * S) {
+            const int j0 = A.col[e], j1 = A.col[e + S], j2 = A.col[e + 2 * S], j3 = A.col[e + 3 * S];
+            const float w0 = A.val[e], w1 = A.val[e + S], w2 = A.val[e + 2 * S], w3 = A.val[e + 3 * S];
+            const Vec<VEC> x0 = vload<VEC>(A.tprev + (size_t)j0 * ldp + colofs);
+            const Vec<VEC> x1 = vload<VEC>(A.tprev + (size_t)j1 * ldp + colofs);
+            const Vec<VEC> x2 = vload<VEC>(A.tprev + (size_t)j2 * ldp + colofs);
+            const Vec<VEC> x3 = vload<VEC>(A.tprev + (size_t)j3 * ldp + colofs);
+            vacc<VEC>(sum, w0, own, x0);
+            vacc<VEC>(sum, w1, own, x1);
+            vacc<VEC>(sum, w2, own, x2);
+            vacc<VEC>(sum, w3, own, x3);
+        }
+        for (; e < end; e += S) {
+            const int j = A.col[e];
+            const float w = A.val[e];
+            vacc<VEC>(sum, w, own, vload<VEC>(A.tprev + (size_t)j * ldp + colofs));
+        }
+    }
+    // combine the S partial sums of a row (lanes lr, lr ^ C, lr ^ 2C, ...)
+#pragma unroll
+    for (int o = C; o < LPR; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) sum.v[i] += __shfl_xor(sum.v[i], o, 64);
+    }
+    if (!valid || s != 0) return;
+
+    const int flags = A.flags;
+    const float alpha = A.coef[0];
+    const float* b = A.coef + 1;
+    const float* db = A.coef + 2 + A.K;
+    Vec<VEC> t, accn, acc2n;
+    if (flags & STEP_FIRST) {
+        const float hb0 = 0.5f * b[0], b1 = b[1];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            t.v[i] = fmaf(alpha, sum.v[i], -own.v[i]);            // T_1 = y X
+            accn.v[i] = fmaf(b1, t.v[i], hb0 * own.v[i]);
+        }
+        if (flags & STEP_DUAL) {
+            const float hd0 = 0.5f * db[0], d1 = db[1];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc2n.v[i] = fmaf(d1, t.v[i], hd0 * own.v[i]);
+        }
+    } else {
+        const float bk = b[A.k];
+        const Vec<VEC> p2 = vload<VEC>(A.tprev2 + off);
+        const Vec<VEC> ac = vload<VEC>(A.acc + off);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const float yx = fmaf(alpha, sum.v[i], -own.v[i]);    // (y T_{k-1})_i
+            t.v[i] = fmaf(2.f, yx, -p2.v[i]);
+            accn.v[i] = fmaf(bk, t.v[i], ac.v[i]);
+        }
+        if (flags & STEP_DUAL) {
+            const float dk = db[A.k];
+            const Vec<VEC> ac2 = vload<VEC>(A.acc2 + off);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc2n.v[i] = fmaf(dk, t.v[i], ac2.v[i]);
+        }
+    }
+    if (flags & STEP_WRITE_T) vstore<VEC>(A.tout + off, t);
+    if (flags & STEP_EPI_SCALE) {
+        const Vec<VEC> nm = vload<VEC>(A.num + off);
+        const float ai = A.a ? A.a[row] : 1.f;
+        const float phi = A.phi;
+        Vec<VEC> dd, o, oa;
+        unsigned cnt = 0;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const float r = accn.v[i];
+            const bool ok = r > phi;
+            dd.v[i] = ok ? r : phi;
+            o.v[i] = nm.v[i] / dd.v[i];
+            oa.v[i] = ai * o.v[i];
+            cnt += (!ok && nm.v[i] > 0.f) ? 1u : 0u;
+        }
+        vstore<VEC>(A.out + off, o);
+        if (A.out_a) vstore<VEC>(A.out_a + off, oa);
+        if (A.rec) vstore<VEC>(A.rec + off, dd);
+        if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
+    } else if (flags & STEP_EPI_STORE) {
+        vstore<VEC>(A.acc + off, accn);
+        if (flags & STEP_DUAL) vstore<VEC>(A.acc2 + off, acc2n);
+    }
+}
+
+template <int VEC, int S, int C>
+void launch_shape(const StepArgs& a, hipStream_t st) {
+    constexpr int RPB = 4 * (64 / (S * C));
+    const int nrt = (a.n + RPB - 1) / RPB;
+    const int nct = a.ldp / (VEC * C);
+    const int grid = nrt * nct;
+    hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C>), dim3(grid), dim3(kBlock), 0, st, a);
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void fill_kernel(float* p, float v, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void copy_ld_kernel(const float* src, int lds, float* dst, int ldd, int64_t n, int B) {
+    const int64_t total = n * (int64_t)ldd;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ldd;
+        const int c = (int)(e - i * ldd);
+        dst[e] = c < B ? src[i * lds + c] : 0.f;
+    }
+}
+
+struct CoefPack {
+    float v[2 * (GS_MAX_K + 1) + 1];
+};
+
+__global__ void set_coef_kernel(float* dcoef, CoefPack pk, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dcoef[i] = pk.v[i];
+}
+
+__global__ void stream_copy_kernel(const float4* src, float4* dst, int64_t n4) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void stream_copy_tail_kernel(const float* src, float* dst, int64_t from, int64_t count) {
+    const int64_t i = from + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i];
+}
+
+int grid_for(int64_t count, int per_block = kBlock) {
+    int64_t g = (count + per_block - 1) / per_block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ K3
+__device__ __forceinline__ double red_term(const ReduceArgs& R, int64_t i, int c) {
+    const size_t e = (size_t)i * R.ldp + c;
+    const double ai = R.a ? (double)R.a[i] : 1.0;
+    switch (R.op) {
+        case RED_DIST: {
+            double s = 0.0;
+            const double mu = R.x0[e], nu = R.x2[e];
+            if (mu > 0.0) s += mu * log((double)R.x1[e]);
+            if (nu > 0.0) s += nu * log((double)R.x3[e]);
+            return ai * s;
+        }
+        case RED_MARG: {
+            const double v = R.x0[e], r = R.x1[e], mu = R.x2[e];
+            return fabs(ai * v * r - ai * mu);
+        }
+        case RED_DOT: {
+            const double y = R.x1 ? (double)R.x1[e] : 1.0;
+            return ai * (double)R.x0[e] * y;
+        }
+        default: {  // RED_DOT_QUOT
+            return ai * (double)R.x0[e] * ((double)R.x1[e] / (double)R.x2[e]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void colreduce_kernel(ReduceArgs R, double* partials, int64_t rows_per_blk) {
+    __shared__ double sh[kBlock];
+    const int CW = R.B < kBlock ? R.B : kBlock;
+    const int nrl = kBlock / CW;
+    const int tid = threadIdx.x;
+    const int ct = blockIdx.y;
+    const int c = ct * CW + tid % CW;
+    const int rl = tid / CW;
+    double acc = 0.0;
+    const int64_t r0 = blockIdx.x * rows_per_blk;
+    int64_t r1 = r0 + rows_per_blk;
+    if (r1 > R.n) r1 = R.n;
+    if (rl < nrl && c < R.B) {
+        for (int64_t i = r0 + rl; i < r1; i += nrl) acc += red_term(R, i, c);
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    if (tid < CW && c < R.B) {
+        double s = 0.0;
+        for (int j = 0; j < nrl; ++j) s += sh[tid + j * CW];
+        partials[(size_t)blockIdx.x * R.B + c] = s;
+    }
+}
+
+__global__ void colreduce_final_kernel(const double* partials, int nblk, int B, double* out, int accumulate,
+                                       double scale) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partials[(size_t)b * B + c];
+    out[c] = (accumulate ? out[c] : 0.0) + scale * s;
+}
+
+// ------------------------------------------------------------------ K4
+__global__ __launch_bounds__(kBlock) void bary_row_kernel(const float* acc, const float* alpha, int64_t n, int ldp,
+                                                          int m, float phi, float* bary, float* w, float* xw,
+                                                          const float* a, unsigned long long* nfloor) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = blockIdx.x * (int64_t)(kBlock / 64) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const size_t base = (size_t)row * ldp;
+    double ls = 0.0;
+    unsigned cnt = 0;
+    for (int s = lane; s < m; s += 64) {
+        const float r = acc[base + s];
+        const float q = r > phi ? r : phi;
+        cnt += r > phi ? 0u : 1u;
+        ls += (double)alpha[s] * log((double)q);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o, 64);
+    const double p = exp(ls);
+    const float ai = a ? a[row] : 1.f;
+    for (int s = lane; s < m; s += 64) {
+        const float r = acc[base + s];
+        const float q = r > phi ? r : phi;
+        const float wv = (float)(p / (double)q);
+        w[base + s] = wv;
+        if (xw) xw[base + s] = ai * wv;
+    }
+    if (lane == 0) bary[row] = (float)p;
+    if (cnt) atomicAdd(nfloor, (unsigned long long)cnt);
+}
+
+// ------------------------------------------------------------------ K5
+// Seeds of the reverse sweep from D = 4t sum a (mu ln v + nu ln w):
+// dmu = 4t a ln v, dnu = 4t a ln w, vbar = 4t a mu / v, wbar = 4t a nu / w
+// (on the supports; g4t carries 4t times the upstream gradient per column).
+__global__ void bwd_seed_kernel(const float* mu, const float* nu, const float* v, const float* w, const float* a,
+                                const float* g4t, int64_t n, int ldp, float* dmu, float* dnu, float* vbar,
+                                float* wbar) {
+    const int64_t total = n * (int64_t)ldp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ldp;
+        const int c = (int)(e - i * ldp);
+        const float s = g4t[c] * (a ? a[i] : 1.f);
+        const float m = mu[e], u = nu[e];
+        dmu[e] = m > 0.f ? s * logf(v[e]) : 0.f;
+        dnu[e] = u > 0.f ? s * logf(w[e]) : 0.f;
+        vbar[e] = m > 0.f ? s * (m / v[e]) : 0.f;
+        wbar[e] = u > 0.f ? s * (u / w[e]) : 0.f;
+    }
+}
+
+// w_j = nu / e_j:  dnu += wbar / e_j;  ebar = -wbar * w_j / e_j * 1[e_j > phi]
+__global__ void bwd_e_kernel(const float* wbar, const float* e_, const float* nu, int64_t total, float phi, float* dnu,
+                             float* ebar) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const float ev = e_[e], wb = wbar[e];
+        const float wj = nu[e] / ev;
+        dnu[e] += wb / ev;
+        ebar[e] = ev > phi ? -(wb * wj) / ev : 0.f;
+    }
+}
+
+// v_j = mu / d_j:  vbar = seed + a z;  dmu += vbar / d_j;  dbar = -vbar * v_j / d_j * 1[d_j > phi]
+__global__ void bwd_d_kernel(const float* z, float* vseed, const float* d_, const float* mu, const float* a, int64_t n,
+                             int ldp, float phi, float* dmu, float* dbar) {
+    const int64_t total = n * (int64_t)ldp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ldp;
+        const float ai = a ? a[i] : 1.f;
+        const float vb = fmaf(ai, z[e], vseed[e]);
+        vseed[e] = 0.f;
+        const float dv = d_[e];
+        const float vj = mu[e] / dv;
+        dmu[e] += vb / dv;
+        dbar[e] = dv > phi ? -(vb * vj) / dv : 0.f;
+    }
+}
+
+__global__ void bwd_w_kernel(const float* z, const float* a, int64_t n, int ldp, float* wbar) {
+    const int64_t total = n * (int64_t)ldp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ldp;
+        wbar[e] = (a ? a[i] : 1.f) * z[e];
+    }
+}
+
+__global__ void mask_support_kernel(const float* h, int64_t total, float* g) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        if (!(h[e] > 0.f)) g[e] = 0.f;
+}
+
+__global__ void mul_a_kernel(const float* x, const float* a, int64_t n, int ldp, float* out) {
+    const int64_t total = n * (int64_t)ldp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = a[e / ldp] * x[e];
+}
+
+// ------------------------------------------------------------------ Lanczos helpers (B = 1)
+__global__ void lap_spmv_kernel(const int32_t* rowptr, const int32_t* col, const float* val, int32_t n,
+                                const float* x, float* y) {
+    const int lane = threadIdx.x & 15;
+    const int row = blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4);
+    float s = 0.f;
+    float xi = 0.f;
+    if (row < n) {
+        xi = x[row];
+        for (int e = rowptr[row] + lane; e < rowptr[row + 1]; e += 16) s = fmaf(val[e], xi - x[col[e]], s);
+    }
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
+    if (row < n && lane == 0) y[row] = s;
+}
+
+__global__ void lanczos_update_kernel(float* z, const float* q, const float* qprev, float alpha, float beta, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = z[i] - alpha * q[i] - beta * qprev[i];
+}
+
+__global__ void scale_kernel(float* dst, const float* src, float s, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = s * src[i];
+}
+
+}  // namespace
+
+// ================================================================== launchers
+bool shape_supported(const LaunchShape& s) {
+    if (s.vec == 1) return s.C == 1 && (s.S == 2 || s.S == 4 || s.S == 8 || s.S == 16 || s.S == 32 || s.S == 64);
+    if (s.vec != 4) return false;
+    const int lpr = s.S * s.C;
+    const bool pow2S = s.S == 1 || s.S == 2 || s.S == 4 || s.S == 8 || s.S == 16;
+    const bool pow2C = s.C == 1 || s.C == 2 || s.C == 4 || s.C == 8 || s.C == 16 || s.C == 32 || s.C == 64;
+    return pow2S && pow2C && lpr <= 64;
+}
+
+std::vector<LaunchShape> candidate_shapes(int ldp) {
+    std::vector<LaunchShape> out;
+    if (ldp == 1) {
+        for (int S : {2, 4, 8, 16, 32, 64}) out.push_back({1, S, 1});
+        return out;
+    }
+    for (int C : {1, 2, 4, 8, 16, 32, 64}) {
+        if ((ldp % (4 * C)) != 0) continue;
+        for (int S : {1, 2, 4, 8, 16}) {
+            LaunchShape s{4, S, C};
+            if (shape_supported(s)) out.push_back(s);
+        }
+    }
+    return out;
+}
+
+#define GS_SHAPE_CASE(V, S_, C_)                       \
+    if (shape.vec == V && shape.S == S_ && shape.C == C_) { \
+        launch_shape<V, S_, C_>(a, st);                \
+        return;                                        \
+    }
+
+void launch_step(const LaunchShape& shape, const StepArgs& a, hipStream_t st) {
+    GS_SHAPE_CASE(1, 2, 1) GS_SHAPE_CASE(1, 4, 1) GS_SHAPE_CASE(1, 8, 1) GS_SHAPE_CASE(1, 16, 1)
+    GS_SHAPE_CASE(1, 32, 1) GS_SHAPE_CASE(1, 64, 1)
+    GS_SHAPE_CASE(4, 1, 1) GS_SHAPE_CASE(4, 2, 1) GS_SHAPE_CASE(4, 4, 1) GS_SHAPE_CASE(4, 8, 1) GS_SHAPE_CASE(4, 16, 1)
+    GS_SHAPE_CASE(4, 1, 2) GS_SHAPE_CASE(4, 2, 2) GS_SHAPE_CASE(4, 4, 2) GS_SHAPE_CASE(4, 8, 2) GS_SHAPE_CASE(4, 16, 2)
+    GS_SHAPE_CASE(4, 1, 4) GS_SHAPE_CASE(4, 2, 4) GS_SHAPE_CASE(4, 4, 4) GS_SHAPE_CASE(4, 8, 4) GS_SHAPE_CASE(4, 16, 4)
+    GS_SHAPE_CASE(4, 1, 8) GS_SHAPE_CASE(4, 2, 8) GS_SHAPE_CASE(4, 4, 8) GS_SHAPE_CASE(4, 8, 8)
+    GS_SHAPE_CASE(4, 1, 16) GS_SHAPE_CASE(4, 2, 16) GS_SHAPE_CASE(4, 4, 16)
+    GS_SHAPE_CASE(4, 1, 32) GS_SHAPE_CASE(4, 2, 32)
+    GS_SHAPE_CASE(4, 1, 64)
+    fail(GS_ERR_INVALID, "unsupported launch shape");
+}
+#undef GS_SHAPE_CASE
+
+void launch_fill(float* p, float v, size_t count, hipStream_t st) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for((int64_t)count)), dim3(kBlock), 0, st, p, v, count);
+}
+
+void launch_copy_ld(const float* src, int lds, float* dst, int ldd, int64_t n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(copy_ld_kernel, dim3(grid_for(n * ldd)), dim3(kBlock), 0, st, src, lds, dst, ldd, n, B);
+}
+
+void launch_set_coef(float* dcoef, double alpha, const double* b, const double* db, int K, hipStream_t st) {
+    CoefPack pk{};
+    pk.v[0] = (float)alpha;
+    for (int k = 0; k <= K; ++k) {
+        pk.v[1 + k] = (float)b[k];
+        pk.v[2 + K + k] = db ? (float)db[k] : 0.f;
+    }
+    hipLaunchKernelGGL(set_coef_kernel, dim3(1), dim3(kBlock), 0, st, dcoef, pk, 2 * (K + 1) + 1);
+}
+
+void launch_stream_copy(const float* src, float* dst, int64_t count, hipStream_t st) {
+    const int64_t n4 = count / 4;
+    if (n4 > 0)
+        hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for(n4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n4);
+    if (count > n4 * 4)
+        hipLaunchKernelGGL(stream_copy_tail_kernel, dim3(1), dim3(kBlock), 0, st, src, dst, n4 * 4, count);
+}
+
+int reduce_blocks(int64_t n) {
+    int64_t nb = (n + 2047) / 2048;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+void launch_reduce(const ReduceArgs& r, double* partials, int nblk, double* out, int accumulate, double scale,
+                   hipStream_t st) {
+    const int CW = r.B < kBlock ? r.B : kBlock;
+    const int nct = (r.B + CW - 1) / CW;
+    const int64_t rows = (r.n + nblk - 1) / nblk;
+    hipLaunchKernelGGL(colreduce_kernel, dim3(nblk, nct), dim3(kBlock), 0, st, r, partials, rows);
+    hipLaunchKernelGGL(colreduce_final_kernel, dim3((r.B + 63) / 64), dim3(64), 0, st, partials, nblk, r.B, out,
+                       accumulate, scale);
+}
+
+void launch_bary_row(const float* acc, const float* alpha, int64_t n, int ldp, int m, float phi, float* bary, float* w,
+                     float* xw, const float* a, unsigned long long* nfloor, hipStream_t st) {
+    const int64_t blocks = (n + 3) / 4;
+    hipLaunchKernelGGL(bary_row_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, acc, alpha, n, ldp, m, phi, bary,
+                       w, xw, a, nfloor);
+}
+
+void launch_bwd_seed(const float* mu, const float* nu, const float* v, const float* w, const float* a,
+                     const float* g4t, int64_t n, int ldp, float* dmu, float* dnu, float* vbar_seed, float* wbar,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(bwd_seed_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, mu, nu, v, w, a, g4t, n, ldp,
+                       dmu, dnu, vbar_seed, wbar);
+}
+
+void launch_bwd_e(const float* wbar, const float* e, const float* nu, int64_t n, int ldp, float phi, float* dnu,
+                  float* ebar, hipStream_t st) {
+    hipLaunchKernelGGL(bwd_e_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, wbar, e, nu, n * (int64_t)ldp, phi,
+                       dnu, ebar);
+}
+
+void launch_bwd_d(const float* z, float* vbar_seed, const float* d, const float* mu, const float* a, int64_t n,
+                  int ldp, float phi, float* dmu, float* dbar, hipStream_t st) {
+    hipLaunchKernelGGL(bwd_d_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, z, vbar_seed, d, mu, a, n, ldp, phi,
+                       dmu, dbar);
+}
+
+void launch_bwd_w(const float* z, const float* a, int64_t n, int ldp, float* wbar, hipStream_t st) {
+    hipLaunchKernelGGL(bwd_w_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, z, a, n, ldp, wbar);
+}
+
+void launch_mask_support(const float* h, int64_t n, int ldp, float* g, hipStream_t st) {
+    hipLaunchKernelGGL(mask_support_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, h, n * (int64_t)ldp, g);
+}
+
+void launch_mul_a(const float* x, const float* a, int64_t n, int ldp, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(mul_a_kernel, dim3(grid_for(n * ldp)), dim3(kBlock), 0, st, x, a, n, ldp, out);
+}
+
+void launch_lap_spmv(const int32_t* rowptr, const int32_t* col, const float* val, int32_t n, const float* x, float* y,
+                     hipStream_t st) {
+    const int blocks = (n + (kBlock / 16) - 1) / (kBlock / 16);
+    hipLaunchKernelGGL(lap_spmv_kernel, dim3(blocks), dim3(kBlock), 0, st, rowptr, col, val, n, x, y);
+}
+
+void launch_lanczos_update(float* z, const float* q, const float* qprev, double alpha, double beta, int64_t n,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(lanczos_update_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, z, q, qprev, (float)alpha,
+                       (float)beta, n);
+}
+
+void launch_scale(float* dst, const float* src, double s, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, src, (float)s, n);
+}
+
+}  // namespace gs

@@ -1,0 +1,562 @@
+// Plans and the host drivers of the hot path: heat application, Algorithm 1,
+// its checkpointed reverse sweep, the barycenter iteration, the step-shape
+// autotuner and hipGraph capture of whole iterations.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <memory>
+#include <sstream>
+
+namespace gs {
+
+namespace {
+
+std::string phi_tag(float phi) {
+    char b[32];
+    std::snprintf(b, sizeof(b), ":%a", (double)phi);
+    return b;
+}
+
+int pad_ld(int B) { return B == 1 ? 1 : ((B + 3) / 4) * 4; }
+
+float* T(gs_plan_s& P, int j) { return (j % 2) ? P.U.p : P.V.p; }
+
+StepArgs base_args(gs_plan_s& P) {
+    StepArgs a{};
+    a.rowptr = P.g->rowptr.p;
+    a.col = P.g->col.p;
+    a.val = P.g->val.p;
+    a.n = (int32_t)P.n;
+    a.ldp = P.ldp;
+    a.coef = P.coef.p;
+    a.K = P.K;
+    a.acc = P.ACC.p;
+    a.acc2 = P.ACC2.p;
+    a.nfloor = P.nfloor.p;
+    return a;
+}
+
+LaunchShape default_shape(int ldp, double nnz_per_row) {
+    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1};
+    int C = 1;
+    while (C * 2 <= 16 && (ldp % (4 * C * 2)) == 0) C *= 2;
+    int S = std::max(1, 8 / C);
+    return {4, S, C};
+}
+
+// Run `body` on `st` directly, or capture it once into a hipGraph (on the
+// plan's private stream) and replay the graph on `st`.
+template <class F>
+void run_graph(gs_plan_s& P, const std::string& key, hipStream_t st, F&& body) {
+    if (P.flags & GS_PLAN_NO_GRAPH) {
+        body(st);
+        GS_HIP(hipGetLastError());
+        return;
+    }
+    auto it = P.graphs.find(key);
+    if (it == P.graphs.end()) {
+        GS_HIP(hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal));
+        try {
+            body(P.cap);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(P.cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hipGraph_t g = nullptr;
+        GS_HIP(hipStreamEndCapture(P.cap, &g));
+        GS_HIP(hipGetLastError());
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            fail(GS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        P.graph_defs[key] = g;
+        it = P.graphs.emplace(key, ex).first;
+    }
+    GS_HIP(hipGraphLaunch(it->second, st));
+}
+
+std::string arch_name() {
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    GS_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string a = prop.gcnArchName;
+    const auto c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// --------------------------------------------------------------- tune cache (flat JSON object)
+std::map<std::string, std::string> read_cache(const std::string& path) {
+    std::map<std::string, std::string> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t k0 = s.find('"', pos);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = s.find('"', k0 + 1);
+        const size_t v0 = s.find('"', k1 + 1);
+        const size_t v1 = v0 == std::string::npos ? v0 : s.find('"', v0 + 1);
+        if (k1 == std::string::npos || v1 == std::string::npos) break;
+        m[s.substr(k0 + 1, k1 - k0 - 1)] = s.substr(v0 + 1, v1 - v0 - 1);
+        pos = v1 + 1;
+    }
+    return m;
+}
+
+void write_cache(const std::string& path, const std::map<std::string, std::string>& m) {
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return;  // a cache that cannot be written is not an error
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) f << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>& be) {
+    const int m = (int)al.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(be[i]) : 0.0);
+        lo = std::min(lo, al[i] - r);
+        hi = std::max(hi, al[i] + r);
+    }
+    auto count_below = [&](double x) {  // Sturm count of eigenvalues < x
+        int c = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            d = al[i] - x - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= m) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
+}  // namespace
+
+}  // namespace gs
+
+gs_plan_s::~gs_plan_s() {
+    gs::drop_graphs(*this);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+namespace gs {
+
+void drop_graphs(gs_plan_s& P) {
+    for (auto& kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : P.graph_defs) (void)hipGraphDestroy(kv.second);
+    P.graphs.clear();
+    P.graph_defs.clear();
+}
+
+void set_coefs(gs_plan_s& P, double lambda_hat, double t, hipStream_t st) {
+    std::vector<double> b(P.K + 1), db(P.K + 1);
+    cheby_coeffs(t, P.K, b.data(), db.data());
+    launch_set_coef(P.coef.p, 2.0 / lambda_hat, b.data(), db.data(), P.K, st);
+}
+
+void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
+    const StepArgs base = base_args(P);
+    for (int k = 1; k <= P.K; ++k) {
+        StepArgs a = base;
+        a.k = k;
+        a.tprev = k == 1 ? X : T(P, k - 1);
+        a.tprev2 = k >= 2 ? (k == 2 ? X : T(P, k - 2)) : nullptr;
+        a.tout = T(P, k);
+        a.phi = phi;
+        int f = 0;
+        if (k == 1) f |= STEP_FIRST;
+        if (mode == ApplyMode::Dual) f |= STEP_DUAL;
+        if (k < P.K) {
+            f |= STEP_WRITE_T | STEP_EPI_STORE;
+        } else if (mode == ApplyMode::Scale) {
+            f |= STEP_EPI_SCALE;
+            a.num = epi.num;
+            a.out = epi.out;
+            a.out_a = epi.out_a;
+            a.a = epi.a;
+            a.rec = epi.rec;
+        } else {
+            f |= STEP_EPI_STORE;
+        }
+        a.flags = f;
+        launch_step(P.shape, a, st);
+    }
+}
+
+double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st) {
+    StepArgs a = base_args(P);
+    a.k = P.K >= 2 ? 2 : 1;
+    a.tprev = P.V.p;
+    a.tprev2 = P.U.p;
+    a.tout = P.U.p;
+    a.flags = STEP_WRITE_T | STEP_EPI_STORE | (a.k == 1 ? STEP_FIRST : 0);
+    for (int i = 0; i < 2; ++i) launch_step(shape, a, st);
+    hipEvent_t e0, e1;
+    GS_HIP(hipEventCreate(&e0));
+    GS_HIP(hipEventCreate(&e1));
+    GS_HIP(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i) launch_step(shape, a, st);
+    GS_HIP(hipEventRecord(e1, st));
+    GS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    GS_HIP(hipGetLastError());
+    return (double)ms / reps;
+}
+
+gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cache) {
+    auto P = std::make_unique<gs_plan_s>();
+    P->g = g;
+    P->K = K;
+    P->B = B;
+    P->ldp = pad_ld(B);
+    P->n = g->n;
+    P->flags = flags;
+    const size_t sz = P->sz();
+    for (auto* b : {&P->X, &P->U, &P->V, &P->ACC, &P->mu, &P->nu, &P->v, &P->w}) b->alloc(sz);
+    P->coef.alloc(2 * (GS_MAX_K + 1) + 1);
+    P->partials.alloc((size_t)reduce_blocks(P->n) * P->ldp);
+    P->red.alloc(P->ldp);
+    P->nfloor.alloc(1);
+    GS_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    for (auto* b : {&P->X, &P->U, &P->V, &P->ACC, &P->mu, &P->nu, &P->v, &P->w}) launch_fill(b->p, 0.f, sz, P->cap);
+    {
+        std::vector<double> b0(K + 1, 0.0);
+        launch_set_coef(P->coef.p, 1.0, b0.data(), b0.data(), K, P->cap);
+    }
+    GS_HIP(hipStreamSynchronize(P->cap));
+
+    const double npr = g->n ? (double)g->nnz / (double)g->n : 0.0;
+    P->shape = default_shape(P->ldp, npr);
+    P->shape_origin = "default";
+    if (flags & GS_PLAN_AUTOTUNE) {
+        const std::string key = arch_name() + ":n=" + std::to_string(P->n) + ":nnz=" + std::to_string(g->nnz) +
+                                ":B=" + std::to_string(B);
+        std::map<std::string, std::string> cache;
+        if (tune_cache) cache = read_cache(tune_cache);
+        const auto hit = cache.find(key);
+        int vv = 0, ss = 0, cc = 0;
+        if (hit != cache.end() && std::sscanf(hit->second.c_str(), "%d,%d,%d", &vv, &ss, &cc) == 3 &&
+            shape_supported({vv, ss, cc}) && (P->ldp % (vv * cc)) == 0 && (vv == 1) == (P->ldp == 1)) {
+            P->shape = {vv, ss, cc};
+            P->shape_origin = "cache";
+        } else {
+            hipStream_t st = P->cap;
+            launch_fill(P->U.p, 0.5f, sz, st);
+            launch_fill(P->V.p, 0.25f, sz, st);
+            launch_fill(P->ACC.p, 0.f, sz, st);
+            std::vector<double> b(K + 1, 0.01), db(K + 1, 0.0);
+            launch_set_coef(P->coef.p, 0.1, b.data(), db.data(), K, st);
+            double best = 1e300;
+            for (const auto& s : candidate_shapes(P->ldp)) {
+                const double ms = time_step(*P, s, 10, st);
+                if (ms < best) {
+                    best = ms;
+                    P->shape = s;
+                }
+            }
+            P->shape_origin = "autotuned";
+            if (tune_cache) {
+                cache[key] = std::to_string(P->shape.vec) + "," + std::to_string(P->shape.S) + "," +
+                             std::to_string(P->shape.C);
+                write_cache(tune_cache, cache);
+            }
+        }
+    }
+    return P.release();
+}
+
+// ------------------------------------------------------------------ heat apply
+void heat_apply(gs_plan_s& P, double lam, double t, const float* X, float* Y, float* Ydt, hipStream_t st) {
+    const bool dual = Ydt != nullptr;
+    if (dual && !P.ACC2.p) P.ACC2.alloc(P.sz());
+    set_coefs(P, lam, t, st);
+    launch_copy_ld(X, P.B, P.X.p, P.ldp, P.n, P.B, st);
+    run_graph(P, dual ? "heat:dual" : "heat", st, [&](hipStream_t s) {
+        enqueue_apply(P, P.X.p, dual ? ApplyMode::Dual : ApplyMode::Store, ScaleEpi{}, 0.f, s);
+    });
+    launch_copy_ld(P.ACC.p, P.ldp, Y, P.B, P.n, P.B, st);
+    if (dual) launch_copy_ld(P.ACC2.p, P.ldp, Ydt, P.B, P.n, P.B, st);
+    GS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+namespace {
+
+void load_inputs(gs_plan_s& P, const float* a, const float* mu, const float* nu, hipStream_t st) {
+    launch_copy_ld(mu, P.B, P.mu.p, P.ldp, P.n, P.B, st);
+    if (nu) launch_copy_ld(nu, P.B, P.nu.p, P.ldp, P.n, P.B, st);
+    if (a) {
+        if (!P.a.p) {
+            P.a.alloc(P.n);
+            P.xv.alloc(P.sz());
+            P.xw.alloc(P.sz());
+        }
+        GS_HIP(hipMemcpyAsync(P.a.p, a, P.n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+}
+
+// One Sinkhorn iteration: v = mu / floor(p_K(a w)), w = nu / floor(p_K(a v)).
+void enqueue_iteration(gs_plan_s& P, bool has_a, float phi, float* rec_d, float* rec_e, hipStream_t s) {
+    ScaleEpi e1{P.mu.p, P.v.p, has_a ? P.xv.p : nullptr, has_a ? P.a.p : nullptr, rec_d};
+    enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Scale, e1, phi, s);
+    ScaleEpi e2{P.nu.p, P.w.p, has_a ? P.xw.p : nullptr, has_a ? P.a.p : nullptr, rec_e};
+    enqueue_apply(P, has_a ? P.xv.p : P.v.p, ApplyMode::Scale, e2, phi, s);
+}
+
+void reduce_to_host(gs_plan_s& P, const ReduceArgs& r, double scale, double* host, hipStream_t st) {
+    launch_reduce(r, P.partials.p, reduce_blocks(P.n), P.red.p, 0, scale, st);
+    GS_HIP(hipMemcpyAsync(host, P.red.p, P.B * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+ReduceArgs red_args(gs_plan_s& P, int op, const float* x0, const float* x1, const float* x2, const float* x3,
+                    const float* a) {
+    ReduceArgs r{};
+    r.op = op;
+    r.n = P.n;
+    r.ldp = P.ldp;
+    r.B = P.B;
+    r.x0 = x0;
+    r.x1 = x1;
+    r.x2 = x2;
+    r.x3 = x3;
+    r.a = a;
+    return r;
+}
+
+}  // namespace
+
+void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J, float phi,
+              int C, float* ckpt, float* v, float* w, double* dist, double* marg, int64_t* nfl, hipStream_t st) {
+    const bool has_a = a != nullptr;
+    set_coefs(P, lam, t, st);
+    load_inputs(P, a, mu, nu, st);
+    launch_fill(P.w.p, 1.f, P.sz(), st);
+    if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
+    GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
+    const std::string key = std::string("fwd:") + (has_a ? "a" : "1") + phi_tag(phi);
+    for (int j = 0; j < J; ++j) {
+        if (ckpt && j % C == 0)
+            launch_copy_ld(P.w.p, P.ldp, ckpt + (size_t)(j / C) * P.n * P.B, P.B, P.n, P.B, st);
+        run_graph(P, key, st, [&](hipStream_t s) { enqueue_iteration(P, has_a, phi, nullptr, nullptr, s); });
+    }
+    const float* ap = has_a ? P.a.p : nullptr;
+    if (dist) reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, dist, st);
+    if (marg) {
+        run_graph(P, std::string("marg:") + (has_a ? "a" : "1") + phi_tag(phi), st, [&](hipStream_t s) {
+            enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Store, ScaleEpi{}, phi, s);
+        });
+        reduce_to_host(P, red_args(P, RED_MARG, P.v.p, P.ACC.p, P.mu.p, nullptr, ap), 1.0, marg, st);
+    }
+    if (v) launch_copy_ld(P.v.p, P.ldp, v, P.B, P.n, P.B, st);
+    if (w) launch_copy_ld(P.w.p, P.ldp, w, P.B, P.n, P.B, st);
+    unsigned long long nf = 0;
+    if (nfl) GS_HIP(hipMemcpyAsync(&nf, P.nfloor.p, sizeof(nf), hipMemcpyDeviceToHost, st));
+    GS_HIP(hipGetLastError());
+    if (dist || marg || nfl) {
+        GS_HIP(hipStreamSynchronize(st));
+        if (nfl) *nfl = (int64_t)nf;
+    }
+}
+
+// ------------------------------------------------------------------ reverse sweep
+void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J,
+                       float phi, int C, const float* ckpt, const double* gd, float* gmu, float* gnu, double* gt,
+                       hipStream_t st) {
+    const bool has_a = a != nullptr;
+    const size_t sz = P.sz();
+    if (!P.ACC2.p) P.ACC2.alloc(sz);
+    if (P.seg_cap < C) {
+        P.segd.alloc(sz * C);
+        P.sege.alloc(sz * C);
+        P.seg_cap = C;
+    }
+    if (!P.dmu.p) {
+        for (auto* b : {&P.dmu, &P.dnu, &P.vseed, &P.wbar, &P.wck}) b->alloc(sz);
+        P.g4t.alloc(P.ldp);
+        P.tbar.alloc(P.ldp);
+    }
+    set_coefs(P, lam, t, st);
+    load_inputs(P, a, mu, nu, st);
+    std::vector<float> g4(P.ldp, 0.f);
+    for (int b = 0; b < P.B; ++b) g4[b] = (float)(4.0 * t * gd[b]);
+    GS_HIP(hipMemcpyAsync(P.g4t.p, g4.data(), P.ldp * sizeof(float), hipMemcpyHostToDevice, st));
+    GS_HIP(hipMemsetAsync(P.tbar.p, 0, P.ldp * sizeof(double), st));
+    GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
+    const float* ap = has_a ? P.a.p : nullptr;
+    const int nseg = (J + C - 1) / C;
+    const int nblk = reduce_blocks(P.n);
+    std::vector<double> D(P.B, 0.0);
+
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int j0 = s * C;
+        const int ns = std::min(J, j0 + C) - j0;
+        launch_copy_ld(ckpt + (size_t)s * P.n * P.B, P.B, P.wck.p, P.ldp, P.n, P.B, st);
+        GS_HIP(hipMemcpyAsync(P.w.p, P.wck.p, sz * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
+        const std::string tag = std::to_string(ns) + (has_a ? ":a" : ":1") + phi_tag(phi);
+        run_graph(P, "rec:" + tag, st, [&](hipStream_t q) {
+            for (int slot = 0; slot < ns; ++slot)
+                enqueue_iteration(P, has_a, phi, P.segd.p + slot * sz, P.sege.p + slot * sz, q);
+        });
+        if (s == nseg - 1) {
+            reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
+            launch_bwd_seed(P.mu.p, P.nu.p, P.v.p, P.w.p, ap, P.g4t.p, P.n, P.ldp, P.dmu.p, P.dnu.p, P.vseed.p,
+                            P.wbar.p, st);
+        }
+        run_graph(P, "adj:" + tag, st, [&](hipStream_t q) {
+            for (int slot = ns - 1; slot >= 0; --slot) {
+                const float* dj = P.segd.p + slot * sz;
+                const float* ej = P.sege.p + slot * sz;
+                // w_j = nu / e_j, e_j = floor(p_K(a v_j))
+                launch_bwd_e(P.wbar.p, ej, P.nu.p, P.n, P.ldp, phi, P.dnu.p, P.X.p, q);
+                enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
+                launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.mu.p, dj, nullptr, ap), P.partials.p, nblk,
+                              P.tbar.p, 1, 1.0, q);
+                // v_j = mu / d_j, d_j = floor(p_K(a w_{j-1}))
+                launch_bwd_d(P.ACC.p, P.vseed.p, dj, P.mu.p, ap, P.n, P.ldp, phi, P.dmu.p, P.X.p, q);
+                enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
+                if (slot > 0)
+                    launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.nu.p, ej - sz, nullptr, ap), P.partials.p,
+                                  nblk, P.tbar.p, 1, 1.0, q);
+                else
+                    launch_reduce(red_args(P, RED_DOT, P.ACC2.p, P.wck.p, nullptr, nullptr, ap), P.partials.p, nblk,
+                                  P.tbar.p, 1, 1.0, q);
+                launch_bwd_w(P.ACC.p, ap, P.n, P.ldp, P.wbar.p, q);
+            }
+        });
+    }
+    launch_mask_support(P.mu.p, P.n, P.ldp, P.dmu.p, st);
+    launch_mask_support(P.nu.p, P.n, P.ldp, P.dnu.p, st);
+    if (gmu) launch_copy_ld(P.dmu.p, P.ldp, gmu, P.B, P.n, P.B, st);
+    if (gnu) launch_copy_ld(P.dnu.p, P.ldp, gnu, P.B, P.n, P.B, st);
+    std::vector<double> tb(P.ldp, 0.0);
+    if (gt) GS_HIP(hipMemcpyAsync(tb.data(), P.tbar.p, P.ldp * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_HIP(hipGetLastError());
+    GS_HIP(hipStreamSynchronize(st));
+    if (gt)
+        for (int b = 0; b < P.B; ++b) gt[b] = tb[b] + gd[b] * D[b] / t;
+}
+
+// ------------------------------------------------------------------ barycenter
+void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float* mus, const double* alpha, int J,
+                float phi, float* bary, float* v, float* w, double* marg, int64_t* nfl, hipStream_t st) {
+    const bool has_a = a != nullptr;
+    if (!P.alpha.p) P.alpha.alloc(P.ldp);
+    if (!P.bary.p) P.bary.alloc(P.n);
+    set_coefs(P, lam, t, st);
+    load_inputs(P, a, mus, nullptr, st);
+    std::vector<float> al(P.ldp, 0.f);
+    for (int i = 0; i < P.B; ++i) al[i] = (float)alpha[i];
+    GS_HIP(hipMemcpyAsync(P.alpha.p, al.data(), P.ldp * sizeof(float), hipMemcpyHostToDevice, st));
+    launch_fill(P.w.p, 1.f, P.sz(), st);
+    if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
+    GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
+    const float* ap = has_a ? P.a.p : nullptr;
+    const std::string key = std::string("bary:") + (has_a ? "a" : "1") + phi_tag(phi);
+    for (int j = 0; j < J; ++j) {
+        run_graph(P, key, st, [&](hipStream_t s) {
+            ScaleEpi e1{P.mu.p, P.v.p, has_a ? P.xv.p : nullptr, ap, nullptr};
+            enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Scale, e1, phi, s);
+            enqueue_apply(P, has_a ? P.xv.p : P.v.p, ApplyMode::Store, ScaleEpi{}, phi, s);
+            launch_bary_row(P.ACC.p, P.alpha.p, P.n, P.ldp, P.B, phi, P.bary.p, P.w.p, has_a ? P.xw.p : nullptr, ap,
+                            P.nfloor.p, s);
+        });
+    }
+    GS_HIP(hipMemcpyAsync(bary, P.bary.p, P.n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (v) launch_copy_ld(P.v.p, P.ldp, v, P.B, P.n, P.B, st);
+    if (w) launch_copy_ld(P.w.p, P.ldp, w, P.B, P.n, P.B, st);
+    if (marg) {
+        run_graph(P, std::string("marg:") + (has_a ? "a" : "1") + phi_tag(phi), st, [&](hipStream_t s) {
+            enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Store, ScaleEpi{}, phi, s);
+        });
+        reduce_to_host(P, red_args(P, RED_MARG, P.v.p, P.ACC.p, P.mu.p, nullptr, ap), 1.0, marg, st);
+    }
+    unsigned long long nf = 0;
+    if (nfl) GS_HIP(hipMemcpyAsync(&nf, P.nfloor.p, sizeof(nf), hipMemcpyDeviceToHost, st));
+    GS_HIP(hipGetLastError());
+    if (marg || nfl) {
+        GS_HIP(hipStreamSynchronize(st));
+        if (nfl) *nfl = (int64_t)nf;
+    }
+}
+
+// ------------------------------------------------------------------ Lanczos estimate of lambda_max
+double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStream_t st) {
+    const int64_t n = g.n;
+    DevBuf<float> q(n), qp(n), z(n);
+    const int nblk = reduce_blocks(n);
+    DevBuf<double> part((size_t)nblk), red(1);
+    std::vector<float> h(n);
+    uint64_t x = seed ? seed : 0x9E3779B97F4A7C15ull;
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {  // splitmix64 -> uniform(-1, 1)
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t y = x;
+        y = (y ^ (y >> 30)) * 0xBF58476D1CE4E5B9ull;
+        y = (y ^ (y >> 27)) * 0x94D049BB133111EBull;
+        y ^= y >> 31;
+        const double u = 2.0 * ((double)(y >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+        h[i] = (float)u;
+        nrm += (double)h[i] * h[i];
+    }
+    const double inv = 1.0 / std::sqrt(nrm);
+    for (auto& e : h) e = (float)(e * inv);
+    GS_HIP(hipMemcpyAsync(q.p, h.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+    launch_fill(qp.p, 0.f, n, st);
+    auto dot = [&](const float* u, const float* v) {
+        ReduceArgs r{};
+        r.op = RED_DOT;
+        r.n = n;
+        r.ldp = 1;
+        r.B = 1;
+        r.x0 = u;
+        r.x1 = v;
+        launch_reduce(r, part.p, nblk, red.p, 0, 1.0, st);
+        double out = 0.0;
+        GS_HIP(hipMemcpyAsync(&out, red.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        GS_HIP(hipStreamSynchronize(st));
+        return out;
+    };
+    std::vector<double> al, be;
+    double beta_prev = 0.0;
+    for (int j = 0; j < iters; ++j) {
+        launch_lap_spmv(g.rowptr.p, g.col.p, g.val.p, (int32_t)n, q.p, z.p, st);
+        const double aj = dot(q.p, z.p);
+        launch_lanczos_update(z.p, q.p, qp.p, aj, beta_prev, n, st);
+        const double bj = std::sqrt(std::max(0.0, dot(z.p, z.p)));
+        al.push_back(aj);
+        if (j == iters - 1 || bj <= 1e-10 * std::max(1.0, std::fabs(aj))) break;
+        be.push_back(bj);
+        launch_scale(qp.p, z.p, 1.0 / bj, n, st);
+        std::swap(q.p, qp.p);
+        beta_prev = bj;
+    }
+    GS_HIP(hipGetLastError());
+    const double theta = tridiag_max_eig(al, be);
+    if (!(theta > 0.0) || !std::isfinite(theta))
+        fail(GS_ERR_SPECTRUM, "Lanczos produced no positive Ritz value (graph without edges?)");
+    return std::min(safety * theta, g.edge_bound);
+}
+
+}  // namespace gs

@@ -1,0 +1,125 @@
+"""GPU parity of the barycenter iteration and of the hand-written backward.
+
+Barycenter: ||p_gpu - p_ref||_1 <= 1e-6.  Gradients: ||g - g_ref||_2 /
+||g_ref||_2 <= 1e-4 on the supports, and sampled coordinates within 1e-4 of
+max(|g_ref_i|, 1e-3 ||g_ref||_inf); the t-gradient within 1e-4 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sinkhorn as osk
+from gpu_common import lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2211_00805_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    X, labels = synth.clusters_on_curve(10, 300, dim=50, sigma=0.1, workload=3)
+    arrs, L, info, A = oracle_csr(X, 15)
+    assert info["n_components"] == 1
+    return X.shape[0], labels, arrs, L
+
+
+def test_barycenter_matches_oracle(gs, clusters):
+    """Reduced twin of the batched barycenter workload: m = 8 inputs, Dirichlet(0.5), K = 40, t = 2."""
+    n, labels, arrs, L = clusters
+    m, K, t, J = 8, 40, 2.0, 40
+    rng = np.random.default_rng(synth.seed_for(3, 2))
+    H, _ = synth.loguniform_support_histograms(n, m, 30, 1500, 0.5, rng)
+    alpha = np.full(m, 1.0 / m)
+    lam = lam_hat_of(L)
+    ref = osk.barycenter(L, lam, t, K, H.astype(np.float64), alpha, J)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, m)
+    bary = torch.empty(n, device="cuda")
+    out = gs.gs_barycenter(plan, lam, t, to_dev(H), alpha, J, bary, want_marg=True, want_floors=True)
+    p = to_host(bary)
+    assert np.abs(p - ref["p"]).sum() <= 1e-6, np.abs(p - ref["p"]).sum()
+    assert out["n_floored"] == ref["n_floored"]
+    np.testing.assert_allclose(out["marg_err"], ref["marg_row"], rtol=0.05, atol=2e-7)
+
+
+def test_barycenter_single_input_is_smoothed_input(gs, clusters):
+    n, labels, arrs, L = clusters
+    K, t = 30, 1.0
+    rng = np.random.default_rng(8)
+    H, _ = synth.loguniform_support_histograms(n, 1, 100, 400, 1.0, rng)
+    lam = lam_hat_of(L)
+    ref = osk.barycenter(L, lam, t, K, H.astype(np.float64), np.array([1.0]), 3)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, 1)
+    bary = torch.empty(n, device="cuda")
+    gs.gs_barycenter(plan, lam, t, to_dev(H), [1.0], 3, bary)
+    assert np.abs(to_host(bary) - ref["p"]).sum() <= 1e-6
+
+
+def _grad_case(n, labels, B, rng):
+    mus, nus = [], []
+    for b in range(B):
+        s = int(rng.integers(0, 6))
+        mu, nu = synth.cluster_block_pair(labels, s, 2, 1.0, rng)
+        mus.append(mu)
+        nus.append(nu)
+    return np.stack(mus, axis=1), np.stack(nus, axis=1)
+
+
+@pytest.mark.parametrize("J,ce", [(20, 10), (23, 10), (12, 5)])
+def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
+    """Batched pairs on adjacent cluster blocks, K = 30, t = 2; segments of ce iterations."""
+    n, labels, arrs, L = clusters
+    B, K, t = 4, 30, 2.0
+    rng = np.random.default_rng(J * 7 + ce)
+    mu, nu = _grad_case(n, labels, B, rng)
+    gd = np.array([1.0, -0.5, 2.0, 0.25])
+    lam = lam_hat_of(L)
+    ref = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, g=gd)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    ckpt = torch.empty(gs.n_checkpoints(J, ce) * n * B, device="cuda")
+    mud, nud = to_dev(mu), to_dev(nu)
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=ce, ckpt=ckpt)
+    assert (np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)).all()
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, gd, grad_mu=gmu, grad_nu=gnu)
+    for got, want, h in ((to_host(gmu).reshape(n, B), ref["dmu"], mu), (to_host(gnu).reshape(n, B), ref["dnu"], nu)):
+        for b in range(B):
+            s = h[:, b] > 0
+            assert np.all(got[~s, b] == 0)
+            rel = np.linalg.norm(got[s, b] - want[s, b]) / np.linalg.norm(want[s, b])
+            assert rel <= 1e-4, (b, rel)
+            idx = np.nonzero(s)[0][:: max(1, s.sum() // 16)][:16]
+            scale = np.maximum(np.abs(want[idx, b]), 1e-3 * np.abs(want[s, b]).max())
+            assert np.all(np.abs(got[idx, b] - want[idx, b]) <= 1e-4 * scale)
+    np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
+
+
+def test_autograd_function(gs, clusters):
+    n, labels, arrs, L = clusters
+    B, K, J, ce = 2, 20, 10, 5
+    rng = np.random.default_rng(77)
+    mu, nu = _grad_case(n, labels, B, rng)
+    lam = lam_hat_of(L)
+    t0 = 1.5
+    ref = osk.sinkhorn_grad(L, lam, t0, K, mu.astype(np.float64), nu.astype(np.float64), J)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    mud = to_dev(mu).requires_grad_(True)
+    nud = to_dev(nu).requires_grad_(True)
+    tt = torch.tensor(t0, dtype=torch.float64, requires_grad=True)
+    D = gs.geodesic_sinkhorn_distance(mud.view(-1), nud.view(-1), tt, plan, lam, J, ce)
+    D.sum().backward()
+    s = mu > 0
+    got = to_host(mud.grad).reshape(n, B)
+    assert np.linalg.norm(got[s] - ref["dmu"][s]) / np.linalg.norm(ref["dmu"][s]) <= 1e-4
+    assert tt.grad.item() == pytest.approx(ref["dt"].sum(), rel=1e-4)
