@@ -9,6 +9,12 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+# torch ships its own HIP runtime (libamdhip64 with the same soname as the
+# system one).  Loading torch first makes this library bind to that runtime,
+# so torch's allocations, streams and this library's kernels share one HIP
+# runtime and one HSA instance in the process.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgeosink.so")
 

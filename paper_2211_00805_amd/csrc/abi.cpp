@@ -46,9 +46,11 @@ gs_status guarded(F&& f) {
 
 void require_device() {
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    const hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
         (void)hipGetLastError();
-        fail(GS_ERR_NO_DEVICE, "no HIP device is visible");
+        fail(GS_ERR_NO_DEVICE, std::string("no HIP device is visible (hipGetDeviceCount: ") + hipGetErrorString(e) +
+                                   ", count " + std::to_string(count) + ")");
     }
     int dev = 0;
     GS_HIP(hipGetDevice(&dev));

@@ -2,7 +2,11 @@
 
 Barycenter: ||p_gpu - p_ref||_1 <= 1e-6.  Gradients: ||g - g_ref||_2 /
 ||g_ref||_2 <= 1e-4 on the supports, and sampled coordinates within 1e-4 of
-max(|g_ref_i|, 1e-3 ||g_ref||_inf); the t-gradient within 1e-4 relative.
+max(|g_ref_i|, 1e-2 ||g_ref||_inf); the t-gradient within 1e-4 relative.
+The per-coordinate floor: float32 gradient entries carry an absolute error
+of a few u * ||g||_inf (u = 2^-24, entries are sums of 4t ln v terms of size
+up to ||g||_inf), so a coordinate that cancels to ~1e-3 ||g||_inf cannot be
+accurate to 1e-4 of itself; 1e-4 * 1e-2 ||g||_inf = 1e-6 ||g||_inf is ~17 u.
 """
 import numpy as np
 import pytest
@@ -99,7 +103,7 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
             rel = np.linalg.norm(got[s, b] - want[s, b]) / np.linalg.norm(want[s, b])
             assert rel <= 1e-4, (b, rel)
             idx = np.nonzero(s)[0][:: max(1, s.sum() // 16)][:16]
-            scale = np.maximum(np.abs(want[idx, b]), 1e-3 * np.abs(want[s, b]).max())
+            scale = np.maximum(np.abs(want[idx, b]), 1e-2 * np.abs(want[s, b]).max())
             assert np.all(np.abs(got[idx, b] - want[idx, b]) <= 1e-4 * scale)
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
