@@ -79,7 +79,9 @@ __device__ __forceinline__ void vacc(Vec<VEC>& sum, float w, const Vec<VEC>& own
 }
 
 // ------------------------------------------------------------------ K1 + K2
-template <int VEC, int S, int C>
+// DUAL selects the adjoint form with a second accumulator (its own symbol, so
+// profiles separate forward steps from adjoint steps).
+template <int VEC, int S, int C, bool DUAL>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
     constexpr int RPW = 64 / LPR;    // rows per wave
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
             t.v[i] = fmaf(alpha, sum.v[i], -own.v[i]);            // T_1 = y X
             accn.v[i] = fmaf(b1, t.v[i], hb0 * own.v[i]);
         }
-        if (flags & STEP_DUAL) {
+        if constexpr (DUAL) {
             const float hd0 = 0.5f * db[0], d1 = db[1];
 #pragma unroll
             for (int i = 0; i < VEC; ++i) acc2n.v[i] = fmaf(d1, t.v[i], hd0 * own.v[i]);
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
             t.v[i] = fmaf(2.f, yx, -p2.v[i]);
             accn.v[i] = fmaf(bk, t.v[i], ac.v[i]);
         }
-        if (flags & STEP_DUAL) {
+        if constexpr (DUAL) {
             const float dk = db[A.k];
             const Vec<VEC> ac2 = vload<VEC>(A.acc2 + off);
 #pragma unroll
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
     } else if (flags & STEP_EPI_STORE) {
         vstore<VEC>(A.acc + off, accn);
-        if (flags & STEP_DUAL) vstore<VEC>(A.acc2 + off, acc2n);
+        if constexpr (DUAL) vstore<VEC>(A.acc2 + off, acc2n);
     }
 }
 
@@ -197,7 +199,10 @@ void launch_shape(const StepArgs& a, hipStream_t st) {
     const int nrt = (a.n + RPB - 1) / RPB;
     const int nct = a.ldp / (VEC * C);
     const int grid = nrt * nct;
-    hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.flags & STEP_DUAL)
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, false>), dim3(grid), dim3(kBlock), 0, st, a);
 }
 
 // ------------------------------------------------------------------ small kernels

@@ -32,6 +32,8 @@ __all__ = [
     "torus_graph",
     "complete_graph",
     "random_dense_like",
+    "loguniform_support_sizes",
+    "histogram_on_random_support",
 ]
 
 
@@ -185,6 +187,19 @@ def loguniform_support_histograms(n: int, m: int, lo: int, hi: int, alpha: float
         nodes = rng.choice(n, size=int(s), replace=False)
         H[:, i] = dirichlet_on_nodes(n, nodes, alpha, rng)
     return H, sizes
+
+
+def loguniform_support_sizes(n: int, m: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Support sizes floor(exp(U[ln lo, ln hi])) of m histograms, clipped to [1, n]."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi), size=m))).astype(np.int64)
+    return np.clip(sizes, 1, n)
+
+
+def histogram_on_random_support(n: int, size: int, alpha: float, seed: int) -> np.ndarray:
+    """One Dirichlet(alpha) histogram on `size` nodes drawn without replacement (own seed)."""
+    rng = np.random.default_rng(seed)
+    return dirichlet_on_nodes(n, rng.choice(n, size=int(size), replace=False), alpha, rng)
 
 
 def random_dense_like(n: int, B: int, rng: np.random.Generator, positive: bool = False) -> np.ndarray:
