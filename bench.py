@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--knn", type=int, default=10)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--probe-only", action="store_true",
+                   help="set up the workload, then only time the fused step kernel and the copy kernel "
+                        "(short run for profilers and counter collection)")
     return p.parse_args()
 
 
@@ -166,6 +169,18 @@ def main():
     plan = gs.Plan(g, K, P, flags=gs.GS_PLAN_AUTOTUNE)
     shape = plan.describe()
     log(f"[setup] plan: {shape}")
+    if args.probe_only:
+        step_ms, step_bytes = gs.gs_plan_time_step(plan, reps=20)
+        nb = 1 << 30
+        src = torch.ones(nb // 4, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            gs.gs_stream_copy(src, dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "fused step x20 + copy of 1 GiB x3", "step_ms": step_ms,
+                          "step_algorithmic_bytes": step_bytes, "copy_bytes_read": nb, "copy_bytes_written": nb,
+                          "plan": shape, "n": n, "nnz": g.nnz, "B": P}), flush=True)
+        return
     nseg = gs.n_checkpoints(J, ce)
     ckpt = torch.empty(nseg * n * P, device=dev)
     gmu = torch.empty(n * P, device=dev)
