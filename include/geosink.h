@@ -226,11 +226,13 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
 /* Measurement helpers                                                        */
 /* ------------------------------------------------------------------------ */
 
-/* Average duration (ms, HIP events on `stream`) of `reps` launches of one
- * fused Chebyshev step (k >= 2, update of T_k and the accumulator) in the
- * plan's launch shape, and its algorithmic bytes per launch:
- * 4(n+1) + 8 nnz + 20 n B (CSR once; gather T_{k-1} once; read T_{k-2};
- * write T_k; read and write the accumulator).  Synchronises `stream`. */
+/* Average duration (ms, HIP events on `stream`) of one launch of the fused
+ * Chebyshev step kernel over `reps` whole applications of p_K (K launches
+ * each) in the plan's launch shape, and the average algorithmic bytes of one
+ * launch: per step the CSR once (4(n+1) + 8 nnz), T_{k-1} once (4nB, the
+ * gathered operand), T_{k-2} (4nB, all steps but the first), T_k (4nB, all
+ * steps but the last) and the accumulator (4nB read and/or written on every
+ * third step and on the last).  Synchronises `stream`. */
 gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms,
                             double* bytes_per_launch);
 

@@ -267,9 +267,7 @@ gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double*
     return guarded([&] {
         GS_REQUIRE(p != nullptr && avg_ms != nullptr, "plan / avg_ms is NULL");
         GS_REQUIRE(reps >= 1, "reps must be >= 1");
-        *avg_ms = time_step(*p, p->shape, reps, stream);
-        if (bytes_per_launch)
-            *bytes_per_launch = 4.0 * (p->n + 1) + 8.0 * p->g->nnz + 20.0 * (double)p->n * p->B;
+        *avg_ms = time_step(*p, p->shape, reps, stream, bytes_per_launch);
     });
 }
 

@@ -69,11 +69,12 @@ double cheby_tail(double t, int K);
 
 // ---------------------------------------------------------------- kernels (kernels.hip)
 enum StepFlags : int32_t {
-    STEP_FIRST = 1,      // k == 1: T_1 = y X, acc = b_0/2 X + b_1 T_1
+    STEP_FIRST = 1,      // k == 1: T_1 = y X (no T_{k-2})
     STEP_WRITE_T = 2,    // store T_k
     STEP_DUAL = 4,       // second accumulator with the d/dt coefficients
-    STEP_EPI_STORE = 8,  // write the accumulator (final or not)
-    STEP_EPI_SCALE = 16  // out = num / floor(acc); out_a = a * out; record floors
+    STEP_ACC_WRITE = 8,  // store the accumulator(s)
+    STEP_EPI_SCALE = 16, // last step: out = num / floor(acc); out_a = a * out; record floors
+    STEP_ACC_READ = 32   // accumulator(s) hold earlier terms (else they start at 0)
 };
 
 struct StepArgs {
@@ -91,6 +92,7 @@ struct StepArgs {
     int32_t k;
     int32_t K;
     int32_t flags;
+    int32_t cmask;        // terms added to the accumulator: 1 T_{k-2}, 2 T_{k-1}, 4 T_k
     // scaling epilogue
     const float* num;
     float* out;

@@ -79,13 +79,29 @@ __device__ __forceinline__ void vacc(Vec<VEC>& sum, float w, const Vec<VEC>& own
 }
 
 // ------------------------------------------------------------------ K1 + K2
+// One block owns RPB consecutive rows and one column tile.  Its CSR range is
+// staged through LDS with coalesced loads; every row's own T_{k-1}, T_{k-2}
+// and accumulator loads are issued before the gathers, and the gathers are
+// issued kUnroll at a time (branch-free: padding entries re-read the row's
+// own value with weight 0), so each row costs three dependent memory round
+// trips.  (L x)_i = d_i x_i - sum_j A_ij x_j with d_i = sum_j A_ij formed in
+// the same loop.  The accumulator is touched only on flush steps (every third
+// step and the last), each adding up to three terms b_{k-2} T_{k-2},
+// b_{k-1} T_{k-1}, b_k T_k that the step already holds.
+//
 // DUAL selects the adjoint form with a second accumulator (its own symbol, so
 // profiles separate forward steps from adjoint steps).
+constexpr int kChunk = 2048;   // staged (col, weight) pairs per block and pass
+constexpr int kUnroll = 8;     // gathers in flight per lane
+
+__device__ __forceinline__ float coef_at(const float* b, int idx) { return idx == 0 ? 0.5f * b[0] : b[idx]; }
+
 template <int VEC, int S, int C, bool DUAL>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
     constexpr int RPW = 64 / LPR;    // rows per wave
     constexpr int RPB = 4 * RPW;     // rows per block
+    __shared__ int2 stage[kChunk];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ldp = A.ldp;
@@ -96,76 +112,96 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int lr = lane % LPR;
     const int s = lr / C;
     const int c = lr - s * C;
-    const int row = rt * RPB + wave * RPW + lane / LPR;
+    const int r0 = rt * RPB;
+    const int r1 = r0 + RPB < A.n ? r0 + RPB : A.n;
+    const int row = r0 + wave * RPW + lane / LPR;
     const bool valid = row < A.n;
-    const size_t off = (size_t)(valid ? row : 0) * ldp + ct * (VEC * C) + c * VEC;
     const int colofs = ct * (VEC * C) + c * VEC;
+    const size_t off = (size_t)(valid ? row : r0) * ldp + colofs;
+    const int flags = A.flags;
 
-    Vec<VEC> own = vzero<VEC>();
-    Vec<VEC> sum = vzero<VEC>();
+    const int eb = A.rowptr[r0];
+    const int ee = A.rowptr[r1];
+    int rs = 0, re = 0;
+    Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
     if (valid) {
+        rs = A.rowptr[row];
+        re = A.rowptr[row + 1];
         own = vload<VEC>(A.tprev + off);
-        int e = A.rowptr[row] + s;
-        const int end = A.rowptr[row + 1];
-        for (; e + 3 * S < end; e += 4 * S) {
-            const int j0 = A.col[e], j1 = A.col[e + S], j2 = A.col[e + 2 * S], j3 = A.col[e + 3 * S];
-            const float w0 = A.val[e], w1 = A.val[e + S], w2 = A.val[e + 2 * S], w3 = A.val[e + 3 * S];
-            const Vec<VEC> x0 = vload<VEC>(A.tprev + (size_t)j0 * ldp + colofs);
-            const Vec<VEC> x1 = vload<VEC>(A.tprev + (size_t)j1 * ldp + colofs);
-            const Vec<VEC> x2 = vload<VEC>(A.tprev + (size_t)j2 * ldp + colofs);
-            const Vec<VEC> x3 = vload<VEC>(A.tprev + (size_t)j3 * ldp + colofs);
-            vacc<VEC>(sum, w0, own, x0);
-            vacc<VEC>(sum, w1, own, x1);
-            vacc<VEC>(sum, w2, own, x2);
-            vacc<VEC>(sum, w3, own, x3);
+        if (!(flags & STEP_FIRST)) p2 = vload<VEC>(A.tprev2 + off);
+        if (flags & STEP_ACC_READ) {
+            ac = vload<VEC>(A.acc + off);
+            if constexpr (DUAL) ac2 = vload<VEC>(A.acc2 + off);
         }
-        for (; e < end; e += S) {
-            const int j = A.col[e];
-            const float w = A.val[e];
-            vacc<VEC>(sum, w, own, vload<VEC>(A.tprev + (size_t)j * ldp + colofs));
+    }
+
+    Vec<VEC> sx = vzero<VEC>();
+    float sw = 0.f;
+    const float* __restrict__ xrow = A.tprev + colofs;
+    const int self = valid ? row : r0;
+    for (int cb = eb; cb < ee; cb += kChunk) {
+        const int cend = cb + kChunk < ee ? cb + kChunk : ee;
+        for (int e = cb + (int)threadIdx.x; e < cend; e += kBlock)
+            stage[e - cb] = make_int2(A.col[e], __float_as_int(A.val[e]));
+        __syncthreads();
+        const int lo = rs > cb ? rs : cb;
+        const int hi = re < cend ? re : cend;
+        if (valid && lo < hi) {
+            // first e >= lo with (e - rs) % S == s
+            int e = lo + (((s - (lo - rs)) % S) + S) % S;
+            for (; e < hi; e += kUnroll * S) {
+                Vec<VEC> x[kUnroll];
+                float w[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int eu = e + u * S;
+                    const bool ok = eu < hi;
+                    const int2 pr = stage[ok ? eu - cb : 0];
+                    const int j = ok ? pr.x : self;
+                    w[u] = ok ? __int_as_float(pr.y) : 0.f;
+                    x[u] = vload<VEC>(xrow + (size_t)j * ldp);
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    sw += w[u];
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], x[u].v[i], sx.v[i]);
+                }
+            }
         }
+        __syncthreads();
     }
     // combine the S partial sums of a row (lanes lr, lr ^ C, lr ^ 2C, ...)
 #pragma unroll
     for (int o = C; o < LPR; o <<= 1) {
+        sw += __shfl_xor(sw, o, 64);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) sum.v[i] += __shfl_xor(sum.v[i], o, 64);
+        for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
     }
     if (!valid || s != 0) return;
 
-    const int flags = A.flags;
+    const int k = A.k;
     const float alpha = A.coef[0];
     const float* b = A.coef + 1;
     const float* db = A.coef + 2 + A.K;
+    const int m = A.cmask;
+    const float c2 = (m & 1) ? coef_at(b, k - 2) : 0.f;
+    const float c1 = (m & 2) ? coef_at(b, k - 1) : 0.f;
+    const float c0 = (m & 4) ? coef_at(b, k) : 0.f;
     Vec<VEC> t, accn, acc2n;
-    if (flags & STEP_FIRST) {
-        const float hb0 = 0.5f * b[0], b1 = b[1];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            t.v[i] = fmaf(alpha, sum.v[i], -own.v[i]);            // T_1 = y X
-            accn.v[i] = fmaf(b1, t.v[i], hb0 * own.v[i]);
-        }
-        if constexpr (DUAL) {
-            const float hd0 = 0.5f * db[0], d1 = db[1];
+    for (int i = 0; i < VEC; ++i) {
+        const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y T_{k-1})_i
+        t.v[i] = (flags & STEP_FIRST) ? yx : fmaf(2.f, yx, -p2.v[i]);
+        accn.v[i] = fmaf(c0, t.v[i], fmaf(c1, own.v[i], fmaf(c2, p2.v[i], ac.v[i])));
+    }
+    if constexpr (DUAL) {
+        const float d2 = (m & 1) ? coef_at(db, k - 2) : 0.f;
+        const float d1 = (m & 2) ? coef_at(db, k - 1) : 0.f;
+        const float d0 = (m & 4) ? coef_at(db, k) : 0.f;
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc2n.v[i] = fmaf(d1, t.v[i], hd0 * own.v[i]);
-        }
-    } else {
-        const float bk = b[A.k];
-        const Vec<VEC> p2 = vload<VEC>(A.tprev2 + off);
-        const Vec<VEC> ac = vload<VEC>(A.acc + off);
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const float yx = fmaf(alpha, sum.v[i], -own.v[i]);    // (y T_{k-1})_i
-            t.v[i] = fmaf(2.f, yx, -p2.v[i]);
-            accn.v[i] = fmaf(bk, t.v[i], ac.v[i]);
-        }
-        if constexpr (DUAL) {
-            const float dk = db[A.k];
-            const Vec<VEC> ac2 = vload<VEC>(A.acc2 + off);
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) acc2n.v[i] = fmaf(dk, t.v[i], ac2.v[i]);
-        }
+        for (int i = 0; i < VEC; ++i)
+            acc2n.v[i] = fmaf(d0, t.v[i], fmaf(d1, own.v[i], fmaf(d2, p2.v[i], ac2.v[i])));
     }
     if (flags & STEP_WRITE_T) vstore<VEC>(A.tout + off, t);
     if (flags & STEP_EPI_SCALE) {
@@ -187,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         if (A.out_a) vstore<VEC>(A.out_a + off, oa);
         if (A.rec) vstore<VEC>(A.rec + off, dd);
         if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
-    } else if (flags & STEP_EPI_STORE) {
+    } else if (flags & STEP_ACC_WRITE) {
         vstore<VEC>(A.acc + off, accn);
         if constexpr (DUAL) vstore<VEC>(A.acc2 + off, acc2n);
     }

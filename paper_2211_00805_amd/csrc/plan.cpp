@@ -172,8 +172,45 @@ void set_coefs(gs_plan_s& P, double lambda_hat, double t, hipStream_t st) {
     launch_set_coef(P.coef.p, 2.0 / lambda_hat, b.data(), db.data(), P.K, st);
 }
 
+std::vector<StepSched> step_schedule(int K, ApplyMode mode) {
+    // Flush the accumulator on steps 2, 5, 8, ... and on the last step; a
+    // flush adds every term since the previous flush (at most T_{k-2}, T_{k-1},
+    // T_k, all of which the step holds).
+    std::vector<StepSched> out(K);
+    int last = -1;  // highest term index already in the accumulator
+    for (int k = 1; k <= K; ++k) {
+        int f = 0, m = 0;
+        if (k == 1) f |= STEP_FIRST;
+        if (mode == ApplyMode::Dual) f |= STEP_DUAL;
+        const bool final = k == K;
+        const bool flush = final || (k >= 2 && (k - 2) % 3 == 0);
+        if (flush) {
+            for (int idx = last + 1; idx <= k; ++idx) m |= idx == k - 2 ? 1 : idx == k - 1 ? 2 : 4;
+            if (last >= 0) f |= STEP_ACC_READ;
+            last = k;
+            f |= (final && mode == ApplyMode::Scale) ? STEP_EPI_SCALE : STEP_ACC_WRITE;
+        }
+        if (!final) f |= STEP_WRITE_T;
+        out[k - 1] = {f, m};
+    }
+    return out;
+}
+
+double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool has_rec) {
+    const double nb = 4.0 * (double)P.n * P.B;
+    const double acc = (sc.flags & STEP_DUAL) ? 2.0 : 1.0;
+    double b = 4.0 * (P.n + 1) + 8.0 * P.g->nnz + nb;  // CSR once, T_{k-1} once
+    if (!(sc.flags & STEP_FIRST)) b += nb;
+    if (sc.flags & STEP_WRITE_T) b += nb;
+    if (sc.flags & STEP_ACC_READ) b += acc * nb;
+    if (sc.flags & STEP_ACC_WRITE) b += acc * nb;
+    if (sc.flags & STEP_EPI_SCALE) b += 2.0 * nb + (has_out_a ? nb : 0.0) + (has_rec ? nb : 0.0);
+    return b;
+}
+
 void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
     const StepArgs base = base_args(P);
+    const std::vector<StepSched> sched = step_schedule(P.K, mode);
     for (int k = 1; k <= P.K; ++k) {
         StepArgs a = base;
         a.k = k;
@@ -181,47 +218,44 @@ void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi&
         a.tprev2 = k >= 2 ? (k == 2 ? X : T(P, k - 2)) : nullptr;
         a.tout = T(P, k);
         a.phi = phi;
-        int f = 0;
-        if (k == 1) f |= STEP_FIRST;
-        if (mode == ApplyMode::Dual) f |= STEP_DUAL;
-        if (k < P.K) {
-            f |= STEP_WRITE_T | STEP_EPI_STORE;
-        } else if (mode == ApplyMode::Scale) {
-            f |= STEP_EPI_SCALE;
+        a.flags = sched[k - 1].flags;
+        a.cmask = sched[k - 1].cmask;
+        if (a.flags & STEP_EPI_SCALE) {
             a.num = epi.num;
             a.out = epi.out;
             a.out_a = epi.out_a;
             a.a = epi.a;
             a.rec = epi.rec;
-        } else {
-            f |= STEP_EPI_STORE;
         }
-        a.flags = f;
         launch_step(P.shape, a, st);
     }
 }
 
-double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st) {
-    StepArgs a = base_args(P);
-    a.k = P.K >= 2 ? 2 : 1;
-    a.tprev = P.V.p;
-    a.tprev2 = P.U.p;
-    a.tout = P.U.p;
-    a.flags = STEP_WRITE_T | STEP_EPI_STORE | (a.k == 1 ? STEP_FIRST : 0);
-    for (int i = 0; i < 2; ++i) launch_step(shape, a, st);
+// Average duration (ms) of one step launch over `reps` whole applications of
+// p_K (accumulator form), and the average algorithmic bytes of a launch.
+double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch) {
+    const LaunchShape saved = P.shape;
+    P.shape = shape;
+    enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     hipEvent_t e0, e1;
     GS_HIP(hipEventCreate(&e0));
     GS_HIP(hipEventCreate(&e1));
     GS_HIP(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i) launch_step(shape, a, st);
+    for (int i = 0; i < reps; ++i) enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     GS_HIP(hipEventRecord(e1, st));
     GS_HIP(hipEventSynchronize(e1));
+    P.shape = saved;
     float ms = 0.f;
     GS_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     GS_HIP(hipGetLastError());
-    return (double)ms / reps;
+    if (bytes_per_launch) {
+        double tot = 0.0;
+        for (const auto& sc : step_schedule(P.K, ApplyMode::Store)) tot += step_bytes(P, sc, false, false);
+        *bytes_per_launch = tot / P.K;
+    }
+    return (double)ms / ((double)reps * P.K);
 }
 
 gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cache) {
@@ -269,7 +303,7 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
             launch_set_coef(P->coef.p, 0.1, b.data(), db.data(), K, st);
             double best = 1e300;
             for (const auto& s : candidate_shapes(P->ldp)) {
-                const double ms = time_step(*P, s, 10, st);
+                const double ms = time_step(*P, s, 2, st, nullptr);
                 if (ms < best) {
                     best = ms;
                     P->shape = s;

@@ -11,6 +11,11 @@ namespace gs {
 
 enum class ApplyMode { Store, Dual, Scale };
 
+struct StepSched {
+    int flags;
+    int cmask;
+};
+
 struct ScaleEpi {
     const float* num = nullptr;
     float* out = nullptr;
@@ -64,7 +69,9 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
 void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float* mus, const double* alpha, int J,
                 float phi, float* bary, float* v, float* w, double* marg, int64_t* nfl, hipStream_t st);
 void drop_graphs(gs_plan_s& P);
-double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st);
+double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch);
+std::vector<StepSched> step_schedule(int K, ApplyMode mode);
+double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool has_rec);
 double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStream_t st);
 
 void build_graph_from_points(const float* X, int64_t n, int d, int k, hipStream_t st, gs_graph_s& g);
