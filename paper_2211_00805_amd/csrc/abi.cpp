@@ -185,7 +185,7 @@ gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const 
 gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr, "plan is NULL");
-        const LaunchShape s{vec, S, C};
+        const LaunchShape s{vec, S, C, p->shape.remap};
         GS_REQUIRE(shape_supported(s), "unsupported launch shape");
         GS_REQUIRE((vec == 1) == (p->ldp == 1), "vec must be 1 exactly when B == 1");
         GS_REQUIRE(p->ldp % (vec * C) == 0, "padded B must be a multiple of vec*C");
@@ -193,6 +193,7 @@ gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
         drop_graphs(*p);
         p->shape = s;
         p->shape_origin = "set";
+        update_long_rows(*p);
     });
 }
 
@@ -200,7 +201,8 @@ gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr && buf != nullptr && len > 0, "bad arguments");
         const std::string s = "vec=" + std::to_string(p->shape.vec) + " S=" + std::to_string(p->shape.S) +
-                              " C=" + std::to_string(p->shape.C) + " ldp=" + std::to_string(p->ldp) +
+                              " C=" + std::to_string(p->shape.C) + " xcd=" + std::to_string(p->shape.remap) +
+                              " ldp=" + std::to_string(p->ldp) +
                               " origin=" + p->shape_origin + ((p->flags & GS_PLAN_NO_GRAPH) ? " graphs=off" : " graphs=on");
         std::strncpy(buf, s.c_str(), len - 1);
         buf[len - 1] = 0;

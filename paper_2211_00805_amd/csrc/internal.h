@@ -93,6 +93,10 @@ struct StepArgs {
     int32_t K;
     int32_t flags;
     int32_t cmask;        // terms added to the accumulator: 1 T_{k-2}, 2 T_{k-1}, 4 T_k
+    int32_t remap;        // 1: give each XCD a contiguous range of row tiles
+    int32_t long_thr;     // rows with more nonzeros go to the long-row kernel (0: none)
+    int32_t nlong;        // number of such rows
+    const int32_t* long_rows;
     // scaling epilogue
     const float* num;
     float* out;
@@ -104,13 +108,17 @@ struct StepArgs {
 };
 
 struct LaunchShape {
-    int vec;   // 1 (float) or 4 (float4)
-    int S;     // lanes splitting a row's nonzeros
-    int C;     // lanes over column groups of `vec` floats
-    bool operator==(const LaunchShape& o) const { return vec == o.vec && S == o.S && C == o.C; }
+    int vec;        // 1 (float) or 4 (float4)
+    int S;          // lanes splitting a row's nonzeros
+    int C;          // lanes over column groups of `vec` floats
+    int remap = 1;  // XCD-contiguous block order
+    bool operator==(const LaunchShape& o) const {
+        return vec == o.vec && S == o.S && C == o.C && remap == o.remap;
+    }
 };
 
 bool shape_supported(const LaunchShape& s);
+int long_row_threshold(const LaunchShape& s);
 std::vector<LaunchShape> candidate_shapes(int ldp);
 void launch_step(const LaunchShape& shape, const StepArgs& a, hipStream_t st);
 

@@ -71,6 +71,33 @@ __device__ __forceinline__ Vec<VEC> vzero() {
     return r;
 }
 
+// Single-use streams (CSR pairs, T_{k-2}, accumulators, numerators) are read
+// and written with non-temporal hints so they do not evict the gathered
+// operand's rows from L2.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> vload_nt(const float* p) {
+    Vec<VEC> r;
+    if constexpr (VEC == 4) {
+        const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+        r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    } else {
+        r.v[0] = __builtin_nontemporal_load(p);
+    }
+    return r;
+}
+
+template <int VEC>
+__device__ __forceinline__ void vstore_nt(float* p, const Vec<VEC>& r) {
+    if constexpr (VEC == 4) {
+        v4f t = {r.v[0], r.v[1], r.v[2], r.v[3]};
+        __builtin_nontemporal_store(t, reinterpret_cast<v4f*>(p));
+    } else {
+        __builtin_nontemporal_store(r.v[0], p);
+    }
+}
+
 // sum += w * (own - x)
 template <int VEC>
 __device__ __forceinline__ void vacc(Vec<VEC>& sum, float w, const Vec<VEC>& own, const Vec<VEC>& x) {
@@ -96,6 +123,73 @@ constexpr int kUnroll = 8;     // gathers in flight per lane
 
 __device__ __forceinline__ float coef_at(const float* b, int idx) { return idx == 0 ? 0.5f * b[0] : b[idx]; }
 
+// Step epilogue for one row and one group of VEC columns: the three-term
+// update, the accumulator flush and (last step) Algorithm 1's scaling.
+template <int VEC, bool DUAL>
+__device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t off, const Vec<VEC>& own,
+                                              const Vec<VEC>& p2, const Vec<VEC>& ac, const Vec<VEC>& ac2,
+                                              const Vec<VEC>& sx, float sw) {
+    const int flags = A.flags;
+    const int k = A.k;
+    const float alpha = A.coef[0];
+    const float* b = A.coef + 1;
+    const float* db = A.coef + 2 + A.K;
+    const int m = A.cmask;
+    const float c2 = (m & 1) ? coef_at(b, k - 2) : 0.f;
+    const float c1 = (m & 2) ? coef_at(b, k - 1) : 0.f;
+    const float c0 = (m & 4) ? coef_at(b, k) : 0.f;
+    Vec<VEC> t, accn, acc2n;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y T_{k-1})_i
+        t.v[i] = (flags & STEP_FIRST) ? yx : fmaf(2.f, yx, -p2.v[i]);
+        accn.v[i] = fmaf(c0, t.v[i], fmaf(c1, own.v[i], fmaf(c2, p2.v[i], ac.v[i])));
+    }
+    if constexpr (DUAL) {
+        const float d2 = (m & 1) ? coef_at(db, k - 2) : 0.f;
+        const float d1 = (m & 2) ? coef_at(db, k - 1) : 0.f;
+        const float d0 = (m & 4) ? coef_at(db, k) : 0.f;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i)
+            acc2n.v[i] = fmaf(d0, t.v[i], fmaf(d1, own.v[i], fmaf(d2, p2.v[i], ac2.v[i])));
+    }
+    if (flags & STEP_WRITE_T) vstore<VEC>(A.tout + off, t);
+    if (flags & STEP_EPI_SCALE) {
+        const Vec<VEC> nm = vload_nt<VEC>(A.num + off);
+        const float ai = A.a ? A.a[row] : 1.f;
+        const float phi = A.phi;
+        Vec<VEC> dd, o, oa;
+        unsigned cnt = 0;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const float r = accn.v[i];
+            const bool ok = r > phi;
+            dd.v[i] = ok ? r : phi;
+            o.v[i] = nm.v[i] / dd.v[i];
+            oa.v[i] = ai * o.v[i];
+            cnt += (!ok && nm.v[i] > 0.f) ? 1u : 0u;
+        }
+        vstore<VEC>(A.out + off, o);
+        if (A.out_a) vstore<VEC>(A.out_a + off, oa);
+        if (A.rec) vstore<VEC>(A.rec + off, dd);
+        if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
+    } else if (flags & STEP_ACC_WRITE) {
+        vstore_nt<VEC>(A.acc + off, accn);
+        if constexpr (DUAL) vstore_nt<VEC>(A.acc2 + off, acc2n);
+    }
+}
+
+template <int VEC, bool DUAL>
+__device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off, Vec<VEC>& own, Vec<VEC>& p2,
+                                                  Vec<VEC>& ac, Vec<VEC>& ac2) {
+    own = vload<VEC>(A.tprev + off);
+    if (!(A.flags & STEP_FIRST)) p2 = vload_nt<VEC>(A.tprev2 + off);
+    if (A.flags & STEP_ACC_READ) {
+        ac = vload_nt<VEC>(A.acc + off);
+        if constexpr (DUAL) ac2 = vload_nt<VEC>(A.acc2 + off);
+    }
+}
+
 template <int VEC, int S, int C, bool DUAL>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
@@ -106,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int wave = threadIdx.x >> 6;
     const int ldp = A.ldp;
     const int ncoltiles = ldp / (VEC * C);
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int L = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int rt = L / ncoltiles;
     const int ct = L - rt * ncoltiles;
     const int lr = lane % LPR;
@@ -118,20 +212,20 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const bool valid = row < A.n;
     const int colofs = ct * (VEC * C) + c * VEC;
     const size_t off = (size_t)(valid ? row : r0) * ldp + colofs;
-    const int flags = A.flags;
 
     const int eb = A.rowptr[r0];
     const int ee = A.rowptr[r1];
     int rs = 0, re = 0;
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
+    bool longrow = false;
     if (valid) {
         rs = A.rowptr[row];
         re = A.rowptr[row + 1];
-        own = vload<VEC>(A.tprev + off);
-        if (!(flags & STEP_FIRST)) p2 = vload<VEC>(A.tprev2 + off);
-        if (flags & STEP_ACC_READ) {
-            ac = vload<VEC>(A.acc + off);
-            if constexpr (DUAL) ac2 = vload<VEC>(A.acc2 + off);
+        longrow = A.long_thr > 0 && re - rs > A.long_thr;
+        if (longrow) {
+            re = rs;   // done by cheb_long_kernel
+        } else {
+            load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
         }
     }
 
@@ -142,7 +236,8 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     for (int cb = eb; cb < ee; cb += kChunk) {
         const int cend = cb + kChunk < ee ? cb + kChunk : ee;
         for (int e = cb + (int)threadIdx.x; e < cend; e += kBlock)
-            stage[e - cb] = make_int2(A.col[e], __float_as_int(A.val[e]));
+            stage[e - cb] = make_int2(__builtin_nontemporal_load(A.col + e),
+                                      __float_as_int(__builtin_nontemporal_load(A.val + e)));
         __syncthreads();
         const int lo = rs > cb ? rs : cb;
         const int hi = re < cend ? re : cend;
@@ -178,54 +273,68 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
     }
-    if (!valid || s != 0) return;
+    if (!valid || s != 0 || longrow) return;
+    step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
+}
 
-    const int k = A.k;
-    const float alpha = A.coef[0];
-    const float* b = A.coef + 1;
-    const float* db = A.coef + 2 + A.K;
-    const int m = A.cmask;
-    const float c2 = (m & 1) ? coef_at(b, k - 2) : 0.f;
-    const float c1 = (m & 2) ? coef_at(b, k - 1) : 0.f;
-    const float c0 = (m & 4) ? coef_at(b, k) : 0.f;
-    Vec<VEC> t, accn, acc2n;
+// Rows with more than A.long_thr nonzeros: one block per row and column tile,
+// 256/C lanes splitting the nonzeros, a block reduction through LDS.
+template <int VEC, int C, bool DUAL>
+__global__ __launch_bounds__(kBlock) void cheb_long_kernel(StepArgs A) {
+    constexpr int SL = kBlock / C;   // lanes over the nonzeros
+    __shared__ float red[4][C][VEC + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int s = tid / C;
+    const int c = tid - s * C;
+    const int row = A.long_rows[blockIdx.x];
+    const int colofs = blockIdx.y * (VEC * C) + c * VEC;
+    const size_t off = (size_t)row * A.ldp + colofs;
+    Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
+    if (s == 0) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
+    const int rs = A.rowptr[row], re = A.rowptr[row + 1];
+    const float* __restrict__ xcol = A.tprev + colofs;
+    Vec<VEC> sx = vzero<VEC>();
+    float sw = 0.f;
+    for (int e = rs + s; e < re; e += kUnroll * SL) {
+        Vec<VEC> xv[kUnroll];
+        float w[kUnroll];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y T_{k-1})_i
-        t.v[i] = (flags & STEP_FIRST) ? yx : fmaf(2.f, yx, -p2.v[i]);
-        accn.v[i] = fmaf(c0, t.v[i], fmaf(c1, own.v[i], fmaf(c2, p2.v[i], ac.v[i])));
-    }
-    if constexpr (DUAL) {
-        const float d2 = (m & 1) ? coef_at(db, k - 2) : 0.f;
-        const float d1 = (m & 2) ? coef_at(db, k - 1) : 0.f;
-        const float d0 = (m & 4) ? coef_at(db, k) : 0.f;
-#pragma unroll
-        for (int i = 0; i < VEC; ++i)
-            acc2n.v[i] = fmaf(d0, t.v[i], fmaf(d1, own.v[i], fmaf(d2, p2.v[i], ac2.v[i])));
-    }
-    if (flags & STEP_WRITE_T) vstore<VEC>(A.tout + off, t);
-    if (flags & STEP_EPI_SCALE) {
-        const Vec<VEC> nm = vload<VEC>(A.num + off);
-        const float ai = A.a ? A.a[row] : 1.f;
-        const float phi = A.phi;
-        Vec<VEC> dd, o, oa;
-        unsigned cnt = 0;
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const float r = accn.v[i];
-            const bool ok = r > phi;
-            dd.v[i] = ok ? r : phi;
-            o.v[i] = nm.v[i] / dd.v[i];
-            oa.v[i] = ai * o.v[i];
-            cnt += (!ok && nm.v[i] > 0.f) ? 1u : 0u;
+        for (int u = 0; u < kUnroll; ++u) {
+            const int eu = e + u * SL;
+            const bool ok = eu < re;
+            const int j = ok ? __builtin_nontemporal_load(A.col + eu) : row;
+            w[u] = ok ? __builtin_nontemporal_load(A.val + eu) : 0.f;
+            xv[u] = vload<VEC>(xcol + (size_t)j * A.ldp);
         }
-        vstore<VEC>(A.out + off, o);
-        if (A.out_a) vstore<VEC>(A.out_a + off, oa);
-        if (A.rec) vstore<VEC>(A.rec + off, dd);
-        if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
-    } else if (flags & STEP_ACC_WRITE) {
-        vstore<VEC>(A.acc + off, accn);
-        if constexpr (DUAL) vstore<VEC>(A.acc2 + off, acc2n);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            sw += w[u];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], xv[u].v[i], sx.v[i]);
+        }
+    }
+#pragma unroll
+    for (int o = C; o < 64; o <<= 1) {
+        sw += __shfl_xor(sw, o, 64);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
+    }
+    if (lane < C) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) red[wave][c][i] = sx.v[i];
+        red[wave][c][VEC] = sw;
+    }
+    __syncthreads();
+    if (tid < C) {
+#pragma unroll
+        for (int wv = 1; wv < 4; ++wv) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) sx.v[i] += red[wv][c][i];
+            sw += red[wv][c][VEC];
+        }
+        step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
     }
 }
 
@@ -239,6 +348,12 @@ void launch_shape(const StepArgs& a, hipStream_t st) {
         hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, true>), dim3(grid), dim3(kBlock), 0, st, a);
     else
         hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.nlong > 0) {
+        if (a.flags & STEP_DUAL)
+            hipLaunchKernelGGL((cheb_long_kernel<VEC, C, true>), dim3(a.nlong, nct), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((cheb_long_kernel<VEC, C, false>), dim3(a.nlong, nct), dim3(kBlock), 0, st, a);
+    }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -475,17 +590,24 @@ bool shape_supported(const LaunchShape& s) {
     return pow2S && pow2C && lpr <= 64;
 }
 
+int long_row_threshold(const LaunchShape& s) {
+    const int t = 4 * kUnroll * s.S;   // rows needing more than four gather batches per lane
+    return t < 64 ? 64 : t;
+}
+
 std::vector<LaunchShape> candidate_shapes(int ldp) {
     std::vector<LaunchShape> out;
-    if (ldp == 1) {
-        for (int S : {2, 4, 8, 16, 32, 64}) out.push_back({1, S, 1});
-        return out;
-    }
-    for (int C : {1, 2, 4, 8, 16, 32, 64}) {
-        if ((ldp % (4 * C)) != 0) continue;
-        for (int S : {1, 2, 4, 8, 16}) {
-            LaunchShape s{4, S, C};
-            if (shape_supported(s)) out.push_back(s);
+    for (int remap : {1, 0}) {
+        if (ldp == 1) {
+            for (int S : {2, 4, 8, 16, 32, 64}) out.push_back({1, S, 1, remap});
+            continue;
+        }
+        for (int C : {1, 2, 4, 8, 16, 32, 64}) {
+            if ((ldp % (4 * C)) != 0) continue;
+            for (int S : {1, 2, 4, 8, 16}) {
+                LaunchShape s{4, S, C, remap};
+                if (shape_supported(s)) out.push_back(s);
+            }
         }
     }
     return out;
@@ -497,7 +619,9 @@ std::vector<LaunchShape> candidate_shapes(int ldp) {
         return;                                        \
     }
 
-void launch_step(const LaunchShape& shape, const StepArgs& a, hipStream_t st) {
+void launch_step(const LaunchShape& shape, const StepArgs& a_in, hipStream_t st) {
+    StepArgs a = a_in;
+    a.remap = shape.remap;
     GS_SHAPE_CASE(1, 2, 1) GS_SHAPE_CASE(1, 4, 1) GS_SHAPE_CASE(1, 8, 1) GS_SHAPE_CASE(1, 16, 1)
     GS_SHAPE_CASE(1, 32, 1) GS_SHAPE_CASE(1, 64, 1)
     GS_SHAPE_CASE(4, 1, 1) GS_SHAPE_CASE(4, 2, 1) GS_SHAPE_CASE(4, 4, 1) GS_SHAPE_CASE(4, 8, 1) GS_SHAPE_CASE(4, 16, 1)

@@ -36,15 +36,18 @@ StepArgs base_args(gs_plan_s& P) {
     a.acc = P.ACC.p;
     a.acc2 = P.ACC2.p;
     a.nfloor = P.nfloor.p;
+    a.long_thr = P.nlong > 0 ? P.long_thr : 0;
+    a.nlong = P.nlong;
+    a.long_rows = P.long_rows.p;
     return a;
 }
 
 LaunchShape default_shape(int ldp, double nnz_per_row) {
-    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1};
+    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1};
     int C = 1;
     while (C * 2 <= 16 && (ldp % (4 * C * 2)) == 0) C *= 2;
     int S = std::max(1, 8 / C);
-    return {4, S, C};
+    return {4, S, C, 1};
 }
 
 // Run `body` on `st` directly, or capture it once into a hipGraph (on the
@@ -159,6 +162,22 @@ gs_plan_s::~gs_plan_s() {
 
 namespace gs {
 
+// Rows whose nonzeros exceed the shape's threshold are processed one block per
+// row by the long-row kernel (a single row group would serialise them).
+void update_long_rows(gs_plan_s& P) {
+    const int thr = long_row_threshold(P.shape);
+    std::vector<int32_t> rows;
+    const auto& rp = P.g->h_rowptr;
+    for (int64_t i = 0; i < P.n; ++i)
+        if (rp[i + 1] - rp[i] > thr) rows.push_back((int32_t)i);
+    P.long_thr = thr;
+    P.nlong = (int)rows.size();
+    if (P.nlong) {
+        if (P.long_rows.count < rows.size()) P.long_rows.alloc(rows.size());
+        GS_HIP(hipMemcpy(P.long_rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+}
+
 void drop_graphs(gs_plan_s& P) {
     for (auto& kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : P.graph_defs) (void)hipGraphDestroy(kv.second);
@@ -236,6 +255,7 @@ void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi&
 double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch) {
     const LaunchShape saved = P.shape;
     P.shape = shape;
+    if (!(shape == saved) || P.long_thr == 0) update_long_rows(P);
     enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     hipEvent_t e0, e1;
     GS_HIP(hipEventCreate(&e0));
@@ -244,7 +264,10 @@ double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t s
     for (int i = 0; i < reps; ++i) enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     GS_HIP(hipEventRecord(e1, st));
     GS_HIP(hipEventSynchronize(e1));
-    P.shape = saved;
+    if (!(shape == saved)) {
+        P.shape = saved;
+        update_long_rows(P);
+    }
     float ms = 0.f;
     GS_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -289,10 +312,10 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
         std::map<std::string, std::string> cache;
         if (tune_cache) cache = read_cache(tune_cache);
         const auto hit = cache.find(key);
-        int vv = 0, ss = 0, cc = 0;
-        if (hit != cache.end() && std::sscanf(hit->second.c_str(), "%d,%d,%d", &vv, &ss, &cc) == 3 &&
-            shape_supported({vv, ss, cc}) && (P->ldp % (vv * cc)) == 0 && (vv == 1) == (P->ldp == 1)) {
-            P->shape = {vv, ss, cc};
+        int vv = 0, ss = 0, cc = 0, rr = 1;
+        if (hit != cache.end() && std::sscanf(hit->second.c_str(), "%d,%d,%d,%d", &vv, &ss, &cc, &rr) == 4 &&
+            shape_supported({vv, ss, cc, rr}) && (P->ldp % (vv * cc)) == 0 && (vv == 1) == (P->ldp == 1)) {
+            P->shape = {vv, ss, cc, rr};
             P->shape_origin = "cache";
         } else {
             hipStream_t st = P->cap;
@@ -312,11 +335,12 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
             P->shape_origin = "autotuned";
             if (tune_cache) {
                 cache[key] = std::to_string(P->shape.vec) + "," + std::to_string(P->shape.S) + "," +
-                             std::to_string(P->shape.C);
+                             std::to_string(P->shape.C) + "," + std::to_string(P->shape.remap);
                 write_cache(tune_cache, cache);
             }
         }
     }
+    update_long_rows(*P);
     return P.release();
 }
 

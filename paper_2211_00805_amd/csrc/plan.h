@@ -39,6 +39,8 @@ struct gs_plan_s {
     // Sinkhorn state (n x ldp) and vertex weights (n)
     gs::DevBuf<float> mu, nu, v, w, xv, xw, a;
     gs::DevBuf<float> coef;
+    gs::DevBuf<int32_t> long_rows;  // rows handled by the long-row kernel for the current shape
+    int nlong = 0, long_thr = 0;
     gs::DevBuf<double> partials, red;
     gs::DevBuf<unsigned long long> nfloor;
     gs::DevBuf<float> alpha;   // barycenter weights (m)
@@ -69,6 +71,7 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
 void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float* mus, const double* alpha, int J,
                 float phi, float* bary, float* v, float* w, double* marg, int64_t* nfl, hipStream_t st);
 void drop_graphs(gs_plan_s& P);
+void update_long_rows(gs_plan_s& P);
 double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch);
 std::vector<StepSched> step_schedule(int K, ApplyMode mode);
 double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool has_rec);

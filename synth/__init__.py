@@ -227,18 +227,24 @@ def _csr_from_undirected(n: int, i: np.ndarray, j: np.ndarray, w: np.ndarray):
 
 
 def random_local_graph(n: int, k: int, window: int, rng: np.random.Generator,
-                       wlo: float = 0.05, whi: float = 1.0):
+                       wlo: float = 0.05, whi: float = 1.0, hubs: int = 0, hub_degree: int = 0):
     """Random symmetric sparse graph with kNN-like size and locality.
 
     Every node i draws k partners uniformly from the `window` ids on either side
     of i (wrapping around), self pairs dropped; the undirected edge set is the
     union of the draws, each edge gets a U(wlo, whi) weight.  Degree profile and
     nonzeros per row resemble a symmetrised kNN graph, gathers stay within a
-    band.  Returns CSR (rowptr int32, col int32, w float32).
+    band.  Optionally `hubs` random nodes are linked to `hub_degree` random
+    nodes each (the high-degree rows of kNN graphs in high dimension).
+    Returns CSR (rowptr int32, col int32, w float32).
     """
     src = np.repeat(np.arange(n, dtype=np.int64), k)
     off = rng.integers(1, window + 1, size=n * k) * rng.choice(np.array([-1, 1]), size=n * k)
     dst = (src + off) % n
+    if hubs:
+        hub_ids = rng.choice(n, size=hubs, replace=False)
+        src = np.concatenate([src, np.repeat(hub_ids, hub_degree)])
+        dst = np.concatenate([dst, rng.integers(0, n, size=hubs * hub_degree)])
     a = np.minimum(src, dst)
     b = np.maximum(src, dst)
     keep = a != b

@@ -117,6 +117,27 @@ def test_heat_apply_every_launch_shape(gs, swiss, B):
         assert err <= heat_tol(K, np.abs(x).max()), (shape, err)
 
 
+@pytest.mark.parametrize("B", [1, 32])
+def test_heat_apply_rows_of_very_high_degree(gs, B):
+    """Hub rows (1500-2900 nonzeros) go through the long-row kernel in every launch shape."""
+    n, K, t = 6000, 7, 1.5
+    arrs = synth.random_local_graph(n, 6, 300, np.random.default_rng(21), hubs=4, hub_degree=2900)
+    assert np.diff(arrs[0]).max() > 1500
+    L = csr_laplacian(n, arrs)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = g.edge_bound
+    x = synth.random_dense_like(n, B, np.random.default_rng(22))
+    ref = heat.heat_apply(L, lam, t, K, x.astype(np.float64))
+    for flags in (0, gs.GS_PLAN_NO_GRAPH):
+        plan = gs.Plan(g, K, B, flags=flags)
+        Y = torch.empty(n * B, device="cuda")
+        for shape in _shapes(B):
+            plan.set_shape(*shape)
+            gs.gs_heat_apply(plan, lam, t, to_dev(x), Y)
+            err = np.abs(to_host(Y).reshape(n, B) - ref).max()
+            assert err <= heat_tol(K, np.abs(x).max()), (shape, err)
+
+
 def test_heat_apply_time_derivative(gs, swiss):
     X, arrs, L, info, A = swiss
     n, K, t, B = 2000, 30, 2.0, 8
