@@ -190,6 +190,68 @@ __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off,
     }
 }
 
+// Rows with more than A.long_thr nonzeros: one block per row and column tile,
+// 256/C lanes splitting the nonzeros, a block reduction through LDS.
+template <int VEC, int C, bool DUAL>
+__device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int ncoltiles, float* red_lds) {
+    constexpr int SL = kBlock / C;   // lanes over the nonzeros
+    float (*red)[C][VEC + 1] = reinterpret_cast<float (*)[C][VEC + 1]>(red_lds);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int s = tid / C;
+    const int c = tid - s * C;
+    const int li = item / ncoltiles;
+    const int row = A.long_rows[li];
+    const int colofs = (item - li * ncoltiles) * (VEC * C) + c * VEC;
+    const size_t off = (size_t)row * A.ldp + colofs;
+    Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
+    if (s == 0) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
+    const int rs = A.rowptr[row], re = A.rowptr[row + 1];
+    const float* __restrict__ xcol = A.tprev + colofs;
+    Vec<VEC> sx = vzero<VEC>();
+    float sw = 0.f;
+    for (int e = rs + s; e < re; e += kUnroll * SL) {
+        Vec<VEC> xv[kUnroll];
+        float w[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int eu = e + u * SL;
+            const bool ok = eu < re;
+            const int j = ok ? __builtin_nontemporal_load(A.col + eu) : row;
+            w[u] = ok ? __builtin_nontemporal_load(A.val + eu) : 0.f;
+            xv[u] = vload<VEC>(xcol + (size_t)j * A.ldp);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            sw += w[u];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], xv[u].v[i], sx.v[i]);
+        }
+    }
+#pragma unroll
+    for (int o = C; o < 64; o <<= 1) {
+        sw += __shfl_xor(sw, o, 64);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
+    }
+    if (lane < C) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) red[wave][c][i] = sx.v[i];
+        red[wave][c][VEC] = sw;
+    }
+    __syncthreads();
+    if (tid < C) {
+#pragma unroll
+        for (int wv = 1; wv < 4; ++wv) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) sx.v[i] += red[wv][c][i];
+            sw += red[wv][c][VEC];
+        }
+        step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
+    }
+}
+
 template <int VEC, int S, int C, bool DUAL>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
@@ -200,7 +262,14 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int wave = threadIdx.x >> 6;
     const int ldp = A.ldp;
     const int ncoltiles = ldp / (VEC * C);
-    const int L = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    // the first blocks take the long rows (dispatched first, they overlap the tiles)
+    const int nlb = A.nlong * ncoltiles;
+    if ((int)blockIdx.x < nlb) {
+        long_row_block<VEC, C, DUAL>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
+        return;
+    }
+    const int bt = (int)blockIdx.x - nlb;
+    const int L = A.remap ? xcd_remap(bt, (int)gridDim.x - nlb) : bt;
     const int rt = L / ncoltiles;
     const int ct = L - rt * ncoltiles;
     const int lr = lane % LPR;
@@ -277,83 +346,16 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
 }
 
-// Rows with more than A.long_thr nonzeros: one block per row and column tile,
-// 256/C lanes splitting the nonzeros, a block reduction through LDS.
-template <int VEC, int C, bool DUAL>
-__global__ __launch_bounds__(kBlock) void cheb_long_kernel(StepArgs A) {
-    constexpr int SL = kBlock / C;   // lanes over the nonzeros
-    __shared__ float red[4][C][VEC + 1];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int s = tid / C;
-    const int c = tid - s * C;
-    const int row = A.long_rows[blockIdx.x];
-    const int colofs = blockIdx.y * (VEC * C) + c * VEC;
-    const size_t off = (size_t)row * A.ldp + colofs;
-    Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
-    if (s == 0) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
-    const int rs = A.rowptr[row], re = A.rowptr[row + 1];
-    const float* __restrict__ xcol = A.tprev + colofs;
-    Vec<VEC> sx = vzero<VEC>();
-    float sw = 0.f;
-    for (int e = rs + s; e < re; e += kUnroll * SL) {
-        Vec<VEC> xv[kUnroll];
-        float w[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int eu = e + u * SL;
-            const bool ok = eu < re;
-            const int j = ok ? __builtin_nontemporal_load(A.col + eu) : row;
-            w[u] = ok ? __builtin_nontemporal_load(A.val + eu) : 0.f;
-            xv[u] = vload<VEC>(xcol + (size_t)j * A.ldp);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            sw += w[u];
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], xv[u].v[i], sx.v[i]);
-        }
-    }
-#pragma unroll
-    for (int o = C; o < 64; o <<= 1) {
-        sw += __shfl_xor(sw, o, 64);
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
-    }
-    if (lane < C) {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) red[wave][c][i] = sx.v[i];
-        red[wave][c][VEC] = sw;
-    }
-    __syncthreads();
-    if (tid < C) {
-#pragma unroll
-        for (int wv = 1; wv < 4; ++wv) {
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) sx.v[i] += red[wv][c][i];
-            sw += red[wv][c][VEC];
-        }
-        step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
-    }
-}
-
 template <int VEC, int S, int C>
 void launch_shape(const StepArgs& a, hipStream_t st) {
     constexpr int RPB = 4 * (64 / (S * C));
     const int nrt = (a.n + RPB - 1) / RPB;
     const int nct = a.ldp / (VEC * C);
-    const int grid = nrt * nct;
+    const int grid = nrt * nct + a.nlong * nct;
     if (a.flags & STEP_DUAL)
         hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, true>), dim3(grid), dim3(kBlock), 0, st, a);
     else
         hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, false>), dim3(grid), dim3(kBlock), 0, st, a);
-    if (a.nlong > 0) {
-        if (a.flags & STEP_DUAL)
-            hipLaunchKernelGGL((cheb_long_kernel<VEC, C, true>), dim3(a.nlong, nct), dim3(kBlock), 0, st, a);
-        else
-            hipLaunchKernelGGL((cheb_long_kernel<VEC, C, false>), dim3(a.nlong, nct), dim3(kBlock), 0, st, a);
-    }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -591,8 +593,8 @@ bool shape_supported(const LaunchShape& s) {
 }
 
 int long_row_threshold(const LaunchShape& s) {
-    const int t = 4 * kUnroll * s.S;   // rows needing more than four gather batches per lane
-    return t < 64 ? 64 : t;
+    const int t = 32 * kUnroll * s.S;   // rows needing more than 32 gather batches per lane
+    return t < 256 ? 256 : t;
 }
 
 std::vector<LaunchShape> candidate_shapes(int ldp) {
