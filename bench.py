@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--knn", type=int, default=10)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the barycenter / plain-forward / Swiss-roll timings")
     p.add_argument("--probe-only", action="store_true",
                    help="set up the workload, then only time the fused step kernel and the copy kernel "
                         "(short run for profilers and counter collection)")
@@ -63,6 +65,14 @@ def parse():
 def kernel_source_hash() -> str:
     with open(os.path.join(ROOT, "paper_2211_00805_amd", "csrc", "kernels.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+TUNE_CACHE = os.path.join(ROOT, "paper_2211_00805_amd", "tune_cache.json")
+
+
+def shape_key(desc: str) -> str:
+    """The launch-shape part of a plan description (vec, S, C, XCD order, ldp)."""
+    return " ".join(w for w in desc.split() if w.split("=")[0] in ("vec", "S", "C", "xcd", "ldp"))
 
 
 def measured_traffic(shape_desc: str, n: int, nnz: int, B: int):
@@ -77,7 +87,7 @@ def measured_traffic(shape_desc: str, n: int, nnz: int, B: int):
     with open(path) as f:
         rec = json.load(f)
     if (rec.get("kernel_sha") != kernel_source_hash() or rec.get("n") != n or rec.get("nnz") != nnz
-            or rec.get("B") != B or rec.get("shape") != shape_desc):
+            or rec.get("B") != B or rec.get("shape") != shape_key(shape_desc)):
         return None
     return rec.get("bytes_per_launch")
 
@@ -113,6 +123,75 @@ def cpu_baseline(nnz_target: int, n: int, K: int, t: float):
                        f"1 Sinkhorn iteration forward + reverse sweep for {B} pairs, K={K}, t={t}, on a "
                        f"synthetic banded graph with n={n}, nnz={int(arrs[1].shape[0])} (workload nnz "
                        f"{nnz_target}); {applies} applies in {dt:.1f} s")}
+
+
+def extra_workloads(gs, synth, np, torch, dev):
+    """Timings of the other paper-shaped workloads (one run each after a warm run).
+
+    barycenter: n ~ 200k (30 clusters x 6667 on a curve in R^50, k = 15), m = 64
+      inputs with log-uniform [1k, 50k] supports and Dirichlet(0.5) weights,
+      alpha = 1/64, K = 40, t = 2, J = 300, all inputs in one multi-RHS launch.
+    plain_forward: n = 100k (20 clusters x 5000, R^50, k = 15), one pair with
+      Dirichlet(1) on clusters 0-3 vs 4-7, K = 30, J = 500, t in {0.5, 2, 8}.
+    swiss_roll: n = 2000 Swiss roll in R^10, k = 10, K = 20, t = 1, uniform
+      histograms on 500 random nodes, J = 200.
+    """
+    out = {}
+    # barycenter
+    X, _ = synth.clusters_on_curve(30, 6667, dim=50, sigma=0.1, workload=3)
+    g = gs.gs_graph_from_points(X, 15)
+    lam = gs.gs_lambda_max(g, iters=60, seed=3, safety=1.01)
+    m, K, t, J = 64, 40, 2.0, 300
+    rng = np.random.default_rng(synth.seed_for(3, 2))
+    H, _ = synth.loguniform_support_histograms(g.n, m, 1000, 50000, 0.5, rng)
+    Hd = torch.from_numpy(H).to(dev)
+    plan = gs.Plan(g, K, m, flags=gs.GS_PLAN_AUTOTUNE)
+    bary = torch.empty(g.n, device=dev)
+    alpha = np.full(m, 1.0 / m)
+    gs.gs_barycenter(plan, lam, t, Hd, alpha, 2, bary)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    gs.gs_barycenter(plan, lam, t, Hd, alpha, J, bary)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - w0
+    out["barycenter"] = {"n": g.n, "nnz": g.nnz, "m": m, "K": K, "iters": J, "seconds": round(dt, 3),
+                         "iterations_per_s": round(J / dt, 1), "applies_per_s": round(2 * m * J / dt, 1),
+                         "plan": plan.describe(), "mass": round(float(bary.sum().item()), 6)}
+    log(f"[extra] barycenter {dt:.2f}s")
+    del plan, g, Hd
+    # plain forward on the cluster-curve graph
+    X, labels = synth.clusters_on_curve(20, 5000, dim=50, sigma=0.1, workload=2)
+    g = gs.gs_graph_from_points(X, 15)
+    lam = gs.gs_lambda_max(g, iters=60, seed=2, safety=1.01)
+    mu, nu = synth.cluster_block_pair(labels, 0, 4, 1.0, np.random.default_rng(synth.seed_for(2, 2)))
+    mud, nud = torch.from_numpy(mu).to(dev), torch.from_numpy(nu).to(dev)
+    plan = gs.Plan(g, 30, 1, flags=gs.GS_PLAN_AUTOTUNE)
+    pf = {"n": g.n, "nnz": g.nnz, "K": 30, "iters": 500, "plan": plan.describe()}
+    for t in (0.5, 2.0, 8.0):
+        gs.gs_sinkhorn(plan, lam, t, mud, nud, 2)
+        w0 = time.perf_counter()
+        r = gs.gs_sinkhorn(plan, lam, t, mud, nud, 500)
+        dt = time.perf_counter() - w0
+        pf[f"t={t}"] = {"ms": round(dt * 1e3, 2), "applies_per_s": round(1000 / dt, 1), "D": float(r["dist"][0])}
+    out["plain_forward"] = pf
+    log("[extra] plain forward done")
+    del plan, g
+    # Swiss roll
+    X = synth.swiss_roll(2000, 10, 0.05, workload=1)
+    g = gs.gs_graph_from_points(X, 10)
+    lam = gs.gs_lambda_max(g, iters=60, seed=1, safety=1.01)
+    rng = np.random.default_rng(synth.seed_for(1, 2))
+    mu = torch.from_numpy(synth.uniform_on_random_nodes(2000, 500, rng)).to(dev)
+    nu = torch.from_numpy(synth.uniform_on_random_nodes(2000, 500, rng)).to(dev)
+    plan = gs.Plan(g, 20, 1, flags=gs.GS_PLAN_AUTOTUNE)
+    gs.gs_sinkhorn(plan, lam, 1.0, mu, nu, 2)
+    w0 = time.perf_counter()
+    r = gs.gs_sinkhorn(plan, lam, 1.0, mu, nu, 200)
+    dt = time.perf_counter() - w0
+    out["swiss_roll"] = {"n": 2000, "nnz": g.nnz, "K": 20, "iters": 200, "ms": round(dt * 1e3, 2),
+                         "launches_per_s": round(2 * 20 * 200 / dt, 0), "D": float(r["dist"][0])}
+    log("[extra] swiss roll done")
+    return out
 
 
 def main():
@@ -166,7 +245,7 @@ def main():
     del Hd
     log(f"[setup] {len(need)} histograms, {nbatch} batches of {P} pairs in {time.perf_counter() - t0:.1f}s")
 
-    plan = gs.Plan(g, K, P, flags=gs.GS_PLAN_AUTOTUNE)
+    plan = gs.Plan(g, K, P, flags=gs.GS_PLAN_AUTOTUNE, tune_cache=TUNE_CACHE)
     shape = plan.describe()
     log(f"[setup] plan: {shape}")
     if args.probe_only:
@@ -179,7 +258,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"probe": "2 applications (K step launches each) + copy of 1 GiB x3", "step_ms": step_ms,
                           "step_algorithmic_bytes": step_bytes, "copy_bytes_read": nb, "copy_bytes_written": nb,
-                          "plan": shape, "n": n, "nnz": g.nnz, "B": P}), flush=True)
+                          "plan": shape, "shape": shape_key(shape), "kernel_sha": kernel_source_hash(),
+                          "n": n, "nnz": g.nnz, "B": P, "K": K}), flush=True)
         return
     nseg = gs.n_checkpoints(J, ce)
     ckpt = torch.empty(nseg * n * P, device=dev)
@@ -247,7 +327,7 @@ def main():
     # ---------------------------------------------------------------- plain single-RHS form
     plain = None
     if not args.no_plain:
-        plan1 = gs.Plan(g, K, 1, flags=gs.GS_PLAN_AUTOTUNE)
+        plan1 = gs.Plan(g, K, 1, flags=gs.GS_PLAN_AUTOTUNE, tune_cache=TUNE_CACHE)
         mu1 = dev_batches[0][0][:, :1].contiguous()
         nu1 = dev_batches[0][1][:, :1].contiguous()
         ck1 = torch.empty(nseg * n, device=dev)
@@ -267,6 +347,10 @@ def main():
         plain = {"applies_per_s": round(4 * J / t1, 1), "ms_per_pair_fwd_bwd": round(t1 * 1e3, 2),
                  "plan": plan1.describe(), "step_gbs_algorithmic": round(s1_bytes / (s1_ms * 1e-3) / 1e9, 1)}
         log(f"[plain] B=1 fwd+bwd {t1:.2f}s -> {4 * J / t1:.0f} applies/s")
+
+    extras = None
+    if not args.no_extras:
+        extras = extra_workloads(gs, synth, np, torch, dev)
 
     # ---------------------------------------------------------------- oracle on the host
     cpu = None
@@ -294,6 +378,7 @@ def main():
         "plain_single_rhs": plain,
         "speedup_batched_vs_plain": round(value / plain["applies_per_s"], 2) if plain else None,
         "graph_build_s": round(t_graph, 2),
+        "other_workloads": extras,
         "results_finite": bool(finite),
     }
     print(json.dumps(line), flush=True)
