@@ -222,6 +222,19 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
                         const double* alpha, int32_t iters, float phi, float* bary, float* v,
                         float* w, double* marg_err, int64_t* n_floored, hipStream_t stream);
 
+/* Expectation of node features under a (not necessarily normalised) signal:
+ * out[c] = sum_i p_i Y[i*d + c] / sum_i p_i, c < d (float64 sums, two
+ * deterministic passes).  The Expected Barycenter Effect (Sec. "Geodesic
+ * Sinkhorn Distances", definition of the barycentric distance and the
+ * Expected Barycenter Effect) is the difference of two such expectations
+ * under two barycenters.
+ *   p  device n floats; Y device n x d float32 (node-major, 1 <= d <= 4096);
+ *   out host d doubles.
+ * Allocates temporary device memory; synchronises `stream`.  Fails with
+ * GS_ERR_NONFINITE when sum_i p_i is zero or not finite. */
+gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, hipStream_t stream,
+                         double* out);
+
 /* ------------------------------------------------------------------------ */
 /* Measurement helpers                                                        */
 /* ------------------------------------------------------------------------ */

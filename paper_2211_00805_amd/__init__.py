@@ -11,10 +11,11 @@ import importlib
 _API = ("Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "gs_abi_version",
         "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs", "gs_cheby_tail_bound",
         "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward", "gs_barycenter",
-        "gs_plan_time_step", "gs_stream_copy", "current_stream", "n_checkpoints")
+        "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream", "n_checkpoints")
 _AUTOGRAD = ("GeoSinkhornDistance", "geodesic_sinkhorn_distance")
+_FAMILIES = ("family_barycenter", "barycentric_distance", "expected_barycenter_effect")
 
-__all__ = list(_API + _AUTOGRAD)
+__all__ = list(_API + _AUTOGRAD + _FAMILIES)
 
 
 def __getattr__(name):
@@ -22,4 +23,6 @@ def __getattr__(name):
         return getattr(importlib.import_module(".api", __name__), name)
     if name in _AUTOGRAD:
         return getattr(importlib.import_module(".autograd", __name__), name)
+    if name in _FAMILIES:
+        return getattr(importlib.import_module(".families", __name__), name)
     raise AttributeError(name)

@@ -20,7 +20,7 @@ __all__ = [
     "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
-    "gs_barycenter", "gs_plan_time_step", "gs_stream_copy", "current_stream",
+    "gs_barycenter", "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream",
 ]
 
 
@@ -242,6 +242,18 @@ def gs_barycenter(plan: Plan, lambda_hat: float, t: float, mus: torch.Tensor, al
         _dev(w, "w", nb), marg.ctypes.data_as(_lib.P_f64) if want_marg else None,
         C.byref(nfl) if want_floors else None, current_stream()))
     return {"marg_err": marg if want_marg else None, "n_floored": nfl.value if want_floors else None}
+
+
+def gs_expectation(p: torch.Tensor, Y: torch.Tensor) -> np.ndarray:
+    """sum_i p_i Y[i, :] / sum_i p_i for device p (n,) and Y (n, d) (or (n,))."""
+    n = p.numel()
+    d = Y.numel() // n
+    if d * n != Y.numel():
+        raise ValueError("Y must have n rows")
+    out = np.zeros(d, dtype=np.float64)
+    check("gs_expectation", lib.gs_expectation(_dev(p, "p"), _dev(Y, "Y"), n, d, current_stream(),
+                                               out.ctypes.data_as(_lib.P_f64)))
+    return out
 
 
 def gs_plan_time_step(plan: Plan, reps: int = 50):

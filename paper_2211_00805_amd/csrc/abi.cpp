@@ -265,6 +265,38 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
     });
 }
 
+gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, hipStream_t stream, double* out) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr && Y != nullptr && out != nullptr, "p / Y / out is NULL");
+        GS_REQUIRE(n >= 1, "n must be >= 1");
+        GS_REQUIRE(d >= 1 && d <= 4096, "d must be in [1, 4096]");
+        require_device();
+        const int nblk = reduce_blocks(n);
+        DevBuf<double> part((size_t)nblk * d), red((size_t)d + 1);
+        ReduceArgs r{};
+        r.op = RED_DOT;      // sum_i p_i Y[i, c]  (p as the row weight)
+        r.n = n;
+        r.ldp = d;
+        r.B = d;
+        r.x0 = Y;
+        r.a = p;
+        launch_reduce(r, part.p, nblk, red.p, 0, 1.0, stream);
+        ReduceArgs mass{};
+        mass.op = RED_DOT;   // sum_i p_i
+        mass.n = n;
+        mass.ldp = 1;
+        mass.B = 1;
+        mass.x0 = p;
+        launch_reduce(mass, part.p, nblk, red.p + d, 0, 1.0, stream);
+        std::vector<double> h((size_t)d + 1);
+        GS_HIP(hipMemcpyAsync(h.data(), red.p, (d + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+        GS_HIP(hipStreamSynchronize(stream));
+        GS_HIP(hipGetLastError());
+        if (!(h[d] != 0.0) || !std::isfinite(h[d])) fail(GS_ERR_NONFINITE, "signal has zero or non-finite mass");
+        for (int c = 0; c < d; ++c) out[c] = h[c] / h[d];
+    });
+}
+
 gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms, double* bytes_per_launch) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr && avg_ms != nullptr, "plan / avg_ms is NULL");
