@@ -135,6 +135,12 @@ def extra_workloads(gs, synth, np, torch, dev):
       Dirichlet(1) on clusters 0-3 vs 4-7, K = 30, J = 500, t in {0.5, 2, 8}.
     swiss_roll: n = 2000 Swiss roll in R^10, k = 10, K = 20, t = 1, uniform
       histograms on 500 random nodes, J = 200.
+    swiss_roll_nn: 15 Gaussians x 10,000 samples on a Swiss roll rotated into
+      R^10 (n = 150k, k = 10), all 105 pairs, K = 50, t = 2, J = 200; graph
+      time and distance time, scores against intrinsic-coordinate ground truth.
+    barycenter_effect: control 10 x N(0, 1), treatment 9 x N(5, 1) + one at
+      -30, 500 samples each in 1-D (k = 10), K = 30, t = 2, J = 100; two
+      barycenters and the effect.
     """
     out = {}
     # barycenter
@@ -191,6 +197,56 @@ def extra_workloads(gs, synth, np, torch, dev):
     out["swiss_roll"] = {"n": 2000, "nnz": g.nnz, "K": 20, "iters": 200, "ms": round(dt * 1e3, 2),
                          "launches_per_s": round(2 * 20 * 200 / dt, 0), "D": float(r["dist"][0])}
     log("[extra] swiss roll done")
+    del plan, g
+    # nearest-Wasserstein-neighbour experiment on the Swiss roll
+    per = 10000
+    X, lab, means = synth.gaussians_on_swiss_roll(15, per)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    g = gs.gs_graph_from_points(X, 10)
+    lam = gs.gs_lambda_max(g, iters=60, seed=5, safety=1.01)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - w0
+    H = np.zeros((g.n, 15), dtype=np.float32)
+    for i in range(15):
+        H[lab == i, i] = 1.0 / per
+    Hd = torch.from_numpy(H).to(dev)
+    gs.distance_matrix(g, lam, 2.0, 50, Hd[:, :3], 2)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    D = gs.distance_matrix(g, lam, 2.0, 50, Hd, 200)
+    torch.cuda.synchronize()
+    t_dist = time.perf_counter() - w0
+    truth = np.linalg.norm(means[:, None] - means[None], axis=2)
+    sc = {k: round(v, 4) for k, v in gs.nn_scores(D, truth).items()}
+    out["swiss_roll_nn"] = {"n": g.n, "nnz": g.nnz, "pairs": 105, "K": 50, "t": 2.0, "iters": 200,
+                            "graph_seconds": round(t_graph, 3), "distance_seconds": round(t_dist, 3),
+                            "total_seconds": round(t_graph + t_dist, 3), "scores": sc}
+    log(f"[extra] swiss roll nn {t_graph:.2f}s + {t_dist:.2f}s {sc}")
+    del g, Hd
+    # Expected Barycenter Effect with an outlier at -30
+    rng = np.random.default_rng(12)
+    control = [rng.normal(0.0, 1.0, 500) for _ in range(10)]
+    treat = [rng.normal(5.0, 1.0, 500) for _ in range(9)] + [rng.normal(-30.0, 1.0, 500)]
+    pts = np.concatenate(control + treat).astype(np.float32)[:, None]
+    Hf = np.zeros((pts.shape[0], 20), dtype=np.float32)
+    for i in range(20):
+        Hf[i * 500:(i + 1) * 500, i] = 1.0 / 500
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    g = gs.gs_graph_from_points(pts, 10)
+    lam = gs.gs_lambda_max(g, iters=60, seed=3, safety=1.01)
+    Hfd = torch.from_numpy(Hf).to(dev)
+    alpha = np.full(10, 0.1)
+    pT = gs.family_barycenter(g, lam, 2.0, 30, Hfd[:, 10:].contiguous(), alpha, 100)
+    pC = gs.family_barycenter(g, lam, 2.0, 30, Hfd[:, :10].contiguous(), alpha, 100)
+    tau = float(gs.expected_barycenter_effect(pT, pC, torch.from_numpy(pts).to(dev))[0])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - w0
+    naive = float(np.mean(np.concatenate(treat)) - np.mean(np.concatenate(control)))
+    out["barycenter_effect"] = {"n": g.n, "outlier": -30.0, "K": 30, "iters": 100, "seconds": round(dt, 3),
+                                "effect": round(tau, 4), "naive_difference_of_means": round(naive, 4)}
+    log(f"[extra] barycenter effect {tau:.4f} (naive {naive:.4f}) {dt:.2f}s")
     return out
 
 

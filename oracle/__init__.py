@@ -17,4 +17,4 @@ arithmetic).
 Readings of points the paper leaves silent or garbled are documented in each
 function; the same list is kept with the design notes.
 """
-from . import graph, heat, spectrum, sinkhorn, closed_forms, families  # noqa: F401
+from . import graph, heat, spectrum, sinkhorn, closed_forms, families, pairwise  # noqa: F401

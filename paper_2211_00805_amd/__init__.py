@@ -14,8 +14,9 @@ _API = ("Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH",
         "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream", "n_checkpoints")
 _AUTOGRAD = ("GeoSinkhornDistance", "geodesic_sinkhorn_distance")
 _FAMILIES = ("family_barycenter", "barycentric_distance", "expected_barycenter_effect")
+_PAIRWISE = ("distance_matrix", "nn_scores", "precision_at_k", "pair_list")
 
-__all__ = list(_API + _AUTOGRAD + _FAMILIES)
+__all__ = list(_API + _AUTOGRAD + _FAMILIES + _PAIRWISE)
 
 
 def __getattr__(name):
@@ -25,4 +26,6 @@ def __getattr__(name):
         return getattr(importlib.import_module(".autograd", __name__), name)
     if name in _FAMILIES:
         return getattr(importlib.import_module(".families", __name__), name)
+    if name in _PAIRWISE:
+        return getattr(importlib.import_module(".pairwise", __name__), name)
     raise AttributeError(name)

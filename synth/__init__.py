@@ -21,6 +21,7 @@ __all__ = [
     "sha256",
     "seed_for",
     "swiss_roll",
+    "gaussians_on_swiss_roll",
     "clusters_on_curve",
     "clusters_on_surface",
     "uniform_on_random_nodes",
@@ -71,6 +72,50 @@ def swiss_roll(n: int = 2000, dim: int = 10, noise: float = 0.05, workload: int 
     q, _ = np.linalg.qr(lift_rng.standard_normal((dim, 3)))
     pts = roll @ q.T + noise * rng.standard_normal((n, dim))
     return pts.astype(np.float32)
+
+
+def _roll_arclength(u: np.ndarray) -> np.ndarray:
+    """Arc length of the spiral (u cos u, u sin u) from u = 0."""
+    return 0.5 * (u * np.sqrt(1.0 + u * u) + np.arcsinh(u))
+
+
+def _roll_param_of_arclength(s: np.ndarray) -> np.ndarray:
+    """Inverse of _roll_arclength by Newton's method (s > 0)."""
+    u = np.sqrt(2.0 * np.maximum(s, 1e-12))
+    for _ in range(60):
+        u = np.maximum(u - (_roll_arclength(u) - s) / np.sqrt(1.0 + u * u), 1e-9)
+    return u
+
+
+def gaussians_on_swiss_roll(n_dists: int = 15, per_dist: int = 10000, dim: int = 10, sigma: float = 2.5,
+                            noise: float = 0.0, workload: int = 6) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Samples of Gaussian distributions on a Swiss roll, rotated into R^dim.
+
+    Intrinsic coordinates are (arc length s along the spiral u in
+    [1.5 pi, 4.5 pi], height h in [0, 21]); the roll is a developable surface,
+    so geodesic distances are Euclidean in (s, h).  Means are uniform in the
+    strip shrunk by 2 sigma on each side; each distribution draws `per_dist`
+    points mean + N(0, sigma^2 I_2) in (s, h), mapped to (u cos u, h, u sin u)
+    and rotated into R^dim by the Q factor of a Gaussian dim x 3 matrix, plus
+    optional isotropic noise.  Points are emitted distribution by
+    distribution.  Returns (points float32 (n_dists*per_dist, dim),
+    labels int32, means float64 (n_dists, 2) in (s, h)).
+    """
+    rng = np.random.default_rng(seed_for(workload, 0))
+    s_lo, s_hi = _roll_arclength(np.array([1.5 * np.pi, 4.5 * np.pi]))
+    lo = np.array([s_lo + 2 * sigma, 2 * sigma])
+    hi = np.array([s_hi - 2 * sigma, 21.0 - 2 * sigma])
+    means = lo + (hi - lo) * rng.random((n_dists, 2))
+    sh = np.repeat(means, per_dist, axis=0) + sigma * rng.standard_normal((n_dists * per_dist, 2))
+    u = _roll_param_of_arclength(sh[:, 0])
+    roll = np.stack([u * np.cos(u), sh[:, 1], u * np.sin(u)], axis=1)
+    lift_rng = np.random.default_rng(seed_for(workload, 1))
+    q, _ = np.linalg.qr(lift_rng.standard_normal((dim, 3)))
+    pts = roll @ q.T
+    if noise > 0:
+        pts = pts + noise * rng.standard_normal(pts.shape)
+    labels = np.repeat(np.arange(n_dists, dtype=np.int32), per_dist)
+    return pts.astype(np.float32), labels, means
 
 
 def _scale_to_spacing(centers: np.ndarray, spacing: float, pairs: np.ndarray) -> np.ndarray:
