@@ -25,6 +25,19 @@ def poly_at_eigs(lams: np.ndarray, lam_hat: float, t: float, K: int) -> np.ndarr
     return terms.sum(axis=1).reshape(np.shape(lams))
 
 
+def euler_at_eigs(lams: np.ndarray, lam_hat: float, t: float, N: int) -> np.ndarray:
+    """Backward-Euler kernel at Laplacian eigenvalues: (1 + (t/N)(2/lam_hat) lam)^{-N}."""
+    return (1.0 + (t / N) * (2.0 / lam_hat) * np.asarray(lams, dtype=np.float64)) ** (-N)
+
+
+def cycle_euler_apply(n: int, lam_hat: float, t: float, N: int, X: np.ndarray) -> np.ndarray:
+    """(I + (t/N) L_op)^{-N} X on the cycle through its Fourier diagonalisation."""
+    X = np.asarray(X, dtype=np.float64)
+    p = euler_at_eigs(cycle_eigs(n), lam_hat, t, N)
+    shape = (n,) + (1,) * (X.ndim - 1)
+    return np.real(np.fft.ifft(p.reshape(shape) * np.fft.fft(X, axis=0), axis=0))
+
+
 def cycle_eigs(n: int) -> np.ndarray:
     """Eigenvalues 2 - 2 cos(2 pi j / n) of the unit-weight cycle Laplacian (FFT order)."""
     return 2.0 - 2.0 * np.cos(2.0 * np.pi * np.arange(n) / n)

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+from scipy.sparse.linalg import splu
 from scipy.special import ive
 
 
@@ -92,3 +93,21 @@ def heat_dense_poly(L, lam_hat: float, t: float, K: int) -> np.ndarray:
     """The dense matrix p_K(L, t) (tiny n only)."""
     n = L.shape[0]
     return heat_apply(L, lam_hat, t, K, np.eye(n))
+
+
+def euler_apply(L, lam_hat: float, t: float, N: int, X) -> np.ndarray:
+    """(I + (t/N) L_op)^{-N} X: N backward-Euler steps of the heat equation.
+
+    Paper, Sec. "Related work" (heat kernel applied by solving linear systems
+    of the discretised heat equation) and the ground cost of the Euler
+    discretisation next to Proposition "ground cost": with the sign typo read
+    as (I + (t/N) L_op)^{-N}, eps = 4t, and L_op = (2/lam_hat) L as for the
+    Chebyshev kernel.  Each step is an exact sparse LU solve.
+    """
+    n = L.shape[0]
+    A = (sp.identity(n, format="csc") + (t / N) * (2.0 / lam_hat) * sp.csc_matrix(L, dtype=np.float64)).tocsc()
+    lu = splu(A)
+    Y = np.asarray(X, dtype=np.float64)
+    for _ in range(N):
+        Y = lu.solve(Y)
+    return Y

@@ -52,18 +52,20 @@ def _as2d(x):
     return (x[:, None], True) if x.ndim == 1 else (x, False)
 
 
-def sinkhorn(L, lam_hat, t, K, mu, nu, J, a=None, phi=PHI, record=False, marginals=True):
+def sinkhorn(L, lam_hat, t, K, mu, nu, J, a=None, phi=PHI, record=False, marginals=True, apply=None):
     """Algorithm 1.  Returns a dict with D (B,), v, w, marginal errors and floor counts.
 
     marg_row = ||a v p_K(a w) - a mu||_1 (one extra heat application),
     marg_col = ||a w p_K(a v) - a nu||_1 (zero up to floors).
+    `apply` (x -> H x) replaces p_K by another symmetric kernel (e.g. the
+    backward-Euler one); L, lam_hat and K are then unused.
     """
     mu, squeeze = _as2d(mu)
     nu, _ = _as2d(nu)
     n, B = mu.shape
     a = np.ones(n) if a is None else np.asarray(a, dtype=np.float64)
     ac = a[:, None]
-    H = lambda x: heat_apply(L, lam_hat, t, K, x)
+    H = apply if apply is not None else (lambda x: heat_apply(L, lam_hat, t, K, x))
     w = np.ones((n, B))
     v = np.zeros((n, B))
     n_floored = 0
@@ -101,18 +103,19 @@ def row_marginal(L, lam_hat, t, K, v, w, a=None):
     return ac * v * heat_apply(L, lam_hat, t, K, ac * w)
 
 
-def barycenter(L, lam_hat, t, K, mus, alpha, J, a=None, phi=PHI):
+def barycenter(L, lam_hat, t, K, mus, alpha, J, a=None, phi=PHI, apply=None):
     """Fixed-support barycenter by iterative Bregman projections.
 
     mus (n, m), alpha (m,).  Returns dict with p (n,), v, w (n, m) and the
-    per-input row-marginal errors ||a v_i p_K(a w_i) - a mu_i||_1.
+    per-input row-marginal errors ||a v_i p_K(a w_i) - a mu_i||_1.  `apply`
+    replaces p_K as in `sinkhorn`.
     """
     mus = np.asarray(mus, dtype=np.float64)
     alpha = np.asarray(alpha, dtype=np.float64)
     n, m = mus.shape
     a = np.ones(n) if a is None else np.asarray(a, dtype=np.float64)
     ac = a[:, None]
-    H = lambda x: heat_apply(L, lam_hat, t, K, x)
+    H = apply if apply is not None else (lambda x: heat_apply(L, lam_hat, t, K, x))
     w = np.ones((n, m))
     v = np.zeros((n, m))
     p = np.zeros(n)
