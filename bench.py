@@ -137,7 +137,9 @@ def extra_workloads(gs, synth, np, torch, dev):
       histograms on 500 random nodes, J = 200.
     swiss_roll_nn: 15 Gaussians x 10,000 samples on a Swiss roll rotated into
       R^10 (n = 150k, k = 10), all 105 pairs, K = 50, t = 2, J = 200; graph
-      time and distance time, scores against intrinsic-coordinate ground truth.
+      time and distance time, scores against intrinsic-coordinate ground truth;
+      the same pairs with the backward-Euler kernel (N = 10 implicit steps,
+      CG to the automatic iteration count), the paper's comparator.
     barycenter_effect: control 10 x N(0, 1), treatment 9 x N(5, 1) + one at
       -30, 500 samples each in 1-D (k = 10), K = 30, t = 2, J = 100; two
       barycenters and the effect.
@@ -223,7 +225,18 @@ def extra_workloads(gs, synth, np, torch, dev):
                             "graph_seconds": round(t_graph, 3), "distance_seconds": round(t_dist, 3),
                             "total_seconds": round(t_graph + t_dist, 3), "scores": sc}
     log(f"[extra] swiss roll nn {t_graph:.2f}s + {t_dist:.2f}s {sc}")
-    del g, Hd
+    eplan = gs.Plan(g, 50, 32)
+    eplan.set_kernel(gs.GS_KERNEL_EULER, 10)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    De = gs.distance_matrix(g, lam, 2.0, 50, Hd, 200, plan=eplan)
+    torch.cuda.synchronize()
+    t_euler = time.perf_counter() - w0
+    sce = {k: round(v, 4) for k, v in gs.nn_scores(De, truth).items()}
+    out["swiss_roll_nn"]["euler"] = {"N": 10, "plan": eplan.describe(), "distance_seconds": round(t_euler, 3),
+                                     "scores": sce, "time_ratio_vs_chebyshev": round(t_euler / t_dist, 2)}
+    log(f"[extra] swiss roll nn euler {t_euler:.2f}s {sce}")
+    del g, Hd, eplan
     # Expected Barycenter Effect with an outlier at -30
     rng = np.random.default_rng(12)
     control = [rng.normal(0.0, 1.0, 500) for _ in range(10)]

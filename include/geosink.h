@@ -155,7 +155,33 @@ gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const 
  * multiple of vec*C.  Cached hipGraphs of the plan are dropped. */
 gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C);
 
-/* Human-readable description of the chosen launch shape into buf. */
+/* Kernel a plan applies in gs_heat_apply, gs_sinkhorn and gs_barycenter. */
+#define GS_KERNEL_CHEBYSHEV 0 /* p_K(L, t): degree-K Chebyshev sum (default) */
+#define GS_KERNEL_EULER 1     /* backward-Euler (I + (t/N) L_op)^{-N}       */
+
+/* Select the heat-kernel approximation (paper, Sec. "Related work": the heat
+ * kernel applied by solving the linear systems of an implicit discretisation
+ * of the heat equation, N solves per application; the ground cost of that
+ * discretisation is stated next to Proposition "ground cost", whose sign typo
+ * is read as (I + (t/N) L_op)^{-N}, eps = 4t).  L_op = (2/lambda_hat) L as for
+ * the Chebyshev kernel, so each system I + (t/N) L_op has condition number at
+ * most 1 + 2t/N when lambda_hat >= lambda_max.
+ *   kernel   GS_KERNEL_CHEBYSHEV (N, cg_iters ignored) or GS_KERNEL_EULER.
+ *   N        1..1024 implicit steps per application.
+ *   cg_iters 1..1000 conjugate-gradient iterations per solve (from x = 0, all
+ *            columns at once), or 0: per call, the smallest count whose CG
+ *            bound 2 sqrt(kappa) ((sqrt(kappa)-1)/(sqrt(kappa)+1))^m with
+ *            kappa = 1 + 2t/N is below 2^-52 (relative 2-norm error per
+ *            solve).  m iterations reach m hops, and Algorithm 1's logarithms
+ *            depend on small kernel entries far from a support: a bound at
+ *            float32 resolution (1e-7) leaves distances off by ~1e-3.
+ * With GS_KERNEL_EULER, gs_heat_apply's Ydt and gs_sinkhorn_backward fail with
+ * GS_ERR_INVALID (no time derivative or reverse sweep for this kernel);
+ * allocates 3 n x B float buffers on first use; drops cached hipGraphs and
+ * synchronises the device. */
+gs_status gs_plan_set_kernel(gs_plan p, int32_t kernel, int32_t N, int32_t cg_iters);
+
+/* Human-readable description of the chosen launch shape and kernel into buf. */
 gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len);
 
 void gs_plan_destroy(gs_plan p);

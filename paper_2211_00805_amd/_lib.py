@@ -38,6 +38,8 @@ STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_OOM", -3: "GS_ERR_HIP", 
           -5: "GS_ERR_SPECTRUM", -6: "GS_ERR_NONFINITE", -7: "GS_ERR_NO_DEVICE"}
 GS_PLAN_AUTOTUNE = 1
 GS_PLAN_NO_GRAPH = 2
+GS_KERNEL_CHEBYSHEV = 0
+GS_KERNEL_EULER = 1
 GS_MAX_K = 256
 
 _SIGS = {
@@ -54,6 +56,7 @@ _SIGS = {
     "gs_cheby_tail_bound": (C.c_int, [C.c_double, C.c_int32, P_f64]),
     "gs_plan_create": (C.c_int, [c_graph, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(c_plan)]),
     "gs_plan_set_shape": (C.c_int, [c_plan, C.c_int32, C.c_int32, C.c_int32]),
+    "gs_plan_set_kernel": (C.c_int, [c_plan, C.c_int32, C.c_int32, C.c_int32]),
     "gs_plan_describe": (C.c_int, [c_plan, C.c_char_p, C.c_int32]),
     "gs_plan_destroy": (None, [c_plan]),
     "gs_heat_apply": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f32, c_stream]),

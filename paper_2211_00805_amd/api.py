@@ -14,10 +14,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GeoSinkError, check, lib
+from ._lib import GS_KERNEL_CHEBYSHEV, GS_KERNEL_EULER, GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GeoSinkError, check, lib
 
 __all__ = [
-    "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH",
+    "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "GS_KERNEL_CHEBYSHEV", "GS_KERNEL_EULER",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
     "gs_barycenter", "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream",
@@ -150,6 +150,10 @@ class Plan:
     def set_shape(self, vec: int, S: int, C_: int) -> None:
         """gs_plan_set_shape: force the fused step's launch shape."""
         check("gs_plan_set_shape", lib.gs_plan_set_shape(self.handle, int(vec), int(S), int(C_)))
+
+    def set_kernel(self, kernel: int, N: int = 0, cg_iters: int = 0) -> None:
+        """gs_plan_set_kernel: Chebyshev (default) or backward-Euler (N solves of cg_iters CG steps, 0 = auto)."""
+        check("gs_plan_set_kernel", lib.gs_plan_set_kernel(self.handle, int(kernel), int(N), int(cg_iters)))
 
     def describe(self) -> str:
         buf = C.create_string_buffer(256)

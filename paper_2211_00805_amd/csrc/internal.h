@@ -173,6 +173,22 @@ void launch_lanczos_update(float* z, const float* q, const float* qprev, double 
                            int64_t n, hipStream_t st);
 void launch_scale(float* dst, const float* src, double s, int64_t n, hipStream_t st);
 
+// backward-Euler kernel by conjugate gradients (per-column float64 scalars on the device)
+constexpr int kMaxCgBlocks = 1024;    // row blocks of a CG column pass (partials: kMaxCgBlocks x ldp)
+int cg_blocks(int64_t n);
+void launch_cg_init(const float* b, float* x, float* r, float* p, int64_t total, hipStream_t st);
+// out[c] = sum_i a[i, c] b[i, c] (float64)
+void launch_cg_dot(const float* a, const float* b, int64_t n, int ldp, double* partials, double* out,
+                   hipStream_t st);
+// alpha = rr / (-pqn); x += alpha p; r += alpha qn; rr_new[c] = sum_i r[i, c]^2 (float64)
+void launch_cg_update(float* x, float* r, const float* p, const float* qn, const double* rr, const double* pqn,
+                      int64_t n, int ldp, double* partials, double* rr_new, hipStream_t st);
+void launch_cg_dir(const float* r, float* p, const double* rr_old, const double* rr_new, int64_t total, int ldp,
+                   hipStream_t st);
+// out = num / floor(acc) (+ a out, recorded denominators, floor count), as the step epilogue
+void launch_scale_epilogue(const float* acc, const float* num, float* out, float* out_a, const float* a, float* rec,
+                           float phi, unsigned long long* nfloor, int64_t n, int ldp, hipStream_t st);
+
 // kNN candidates (knn.hip): cand (n x kk) int32, candidate ids sorted by fp32 Gram distance
 void launch_knn_candidates(const float* Xc, const float* norms, int64_t n, int d, int kk, int32_t* cand,
                            hipStream_t st);

@@ -59,7 +59,10 @@ void run_graph(gs_plan_s& P, const std::string& key, hipStream_t st, F&& body) {
         GS_HIP(hipGetLastError());
         return;
     }
-    auto it = P.graphs.find(key);
+    const std::string full = P.kernel == GS_KERNEL_EULER
+                                 ? key + ":E" + std::to_string(P.euler_N) + "." + std::to_string(P.cg_m)
+                                 : key;
+    auto it = P.graphs.find(full);
     if (it == P.graphs.end()) {
         GS_HIP(hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal));
         try {
@@ -79,8 +82,8 @@ void run_graph(gs_plan_s& P, const std::string& key, hipStream_t st, F&& body) {
             (void)hipGraphDestroy(g);
             fail(GS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
-        P.graph_defs[key] = g;
-        it = P.graphs.emplace(key, ex).first;
+        P.graph_defs[full] = g;
+        it = P.graphs.emplace(full, ex).first;
     }
     GS_HIP(hipGraphLaunch(it->second, st));
 }
@@ -189,6 +192,43 @@ void set_coefs(gs_plan_s& P, double lambda_hat, double t, hipStream_t st) {
     std::vector<double> b(P.K + 1), db(P.K + 1);
     cheby_coeffs(t, P.K, b.data(), db.data());
     launch_set_coef(P.coef.p, 2.0 / lambda_hat, b.data(), db.data(), P.K, st);
+    if (P.kernel == GS_KERNEL_EULER) {
+        // operator scale -c, c = (t/N)(2/lambda_hat): one first step yields -(I + c L) p
+        launch_fill(P.ecoef.p, (float)(-(t / P.euler_N) * (2.0 / lambda_hat)), 1, st);
+        P.cg_m = P.cg_iters > 0 ? P.cg_iters : euler_cg_iterations(t, P.euler_N);
+    }
+}
+
+// Conjugate-gradient iterations per backward-Euler solve: with L_op's
+// spectrum in [0, 2], (I + (t/N) L_op) has condition number kappa <= 1 + 2t/N,
+// and after m iterations from x = 0 the error is at most
+// 2 sqrt(kappa) ((sqrt(kappa) - 1)/(sqrt(kappa) + 1))^m ||b||_2.  CG from zero
+// is a degree-m polynomial in the system matrix, so a solve reaches m hops;
+// the exact kernel is positive on every node, and Algorithm 1 takes logarithms
+// of its small entries, so m is the smallest count that brings the bound below
+// 2^-52 (well under float32 resolution), not merely below float32 resolution.
+int euler_cg_iterations(double t, int N) {
+    const double sk = std::sqrt(1.0 + 2.0 * t / N);
+    const double rho = (sk - 1.0) / (sk + 1.0);
+    if (!(rho > 0.0)) return 1;
+    const double m = std::log(2.0 * sk / 0x1p-52) / std::log(1.0 / rho);
+    return std::max(1, (int)std::ceil(m));
+}
+
+void set_kernel(gs_plan_s& P, int kernel, int N, int cg_iters) {
+    drop_graphs(P);
+    P.kernel = kernel;
+    P.euler_N = kernel == GS_KERNEL_EULER ? N : 0;
+    P.cg_iters = kernel == GS_KERNEL_EULER ? cg_iters : 0;
+    P.cg_m = P.cg_iters;
+    if (kernel == GS_KERNEL_EULER && !P.er.p) {
+        for (auto* b : {&P.er, &P.ep, &P.eq}) b->alloc(P.sz());
+        P.ecoef.alloc(2 * (GS_MAX_K + 1) + 1);
+        P.ers.alloc((3 + (size_t)kMaxCgBlocks) * P.ldp);
+        for (auto* b : {&P.er, &P.ep, &P.eq}) launch_fill(b->p, 0.f, P.sz(), P.cap);
+        launch_fill(P.ecoef.p, 0.f, P.ecoef.count, P.cap);
+        GS_HIP(hipStreamSynchronize(P.cap));
+    }
 }
 
 std::vector<StepSched> step_schedule(int K, ApplyMode mode) {
@@ -227,7 +267,10 @@ double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool 
     return b;
 }
 
-void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
+namespace {
+
+void enqueue_cheb_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi,
+                        hipStream_t st) {
     const StepArgs base = base_args(P);
     const std::vector<StepSched> sched = step_schedule(P.K, mode);
     for (int k = 1; k <= P.K; ++k) {
@@ -250,18 +293,64 @@ void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi&
     }
 }
 
+// (I + c L)^{-N} X into ACC: N solves, each cg_m CG iterations from x = 0 on
+// all columns; the right-hand side of a solve is the previous solution.
+void enqueue_euler_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi,
+                         hipStream_t st) {
+    if (mode == ApplyMode::Dual) fail(GS_ERR_INVALID, "the backward-Euler kernel has no time-derivative form");
+    StepArgs mv = base_args(P);
+    mv.coef = P.ecoef.p;
+    mv.k = 1;
+    mv.flags = STEP_FIRST | STEP_WRITE_T;
+    mv.cmask = 0;
+    mv.tprev = P.ep.p;
+    mv.tprev2 = nullptr;
+    mv.tout = P.eq.p;
+    const int64_t total = P.n * (int64_t)P.ldp;
+    double* rr[2] = {P.ers.p, P.ers.p + P.ldp};
+    double* pq = P.ers.p + 2 * P.ldp;
+    double* part = P.ers.p + 3 * P.ldp;
+    const float* rhs = X;
+    for (int s = 0; s < P.euler_N; ++s) {
+        launch_cg_init(rhs, P.ACC.p, P.er.p, P.ep.p, total, st);
+        launch_cg_dot(P.er.p, P.er.p, P.n, P.ldp, part, rr[0], st);
+        int cur = 0;
+        for (int it = 0; it < P.cg_m; ++it) {
+            launch_step(P.shape, mv, st);
+            launch_cg_dot(P.ep.p, P.eq.p, P.n, P.ldp, part, pq, st);
+            launch_cg_update(P.ACC.p, P.er.p, P.ep.p, P.eq.p, rr[cur], pq, P.n, P.ldp, part, rr[1 - cur], st);
+            if (it + 1 < P.cg_m) {
+                launch_cg_dir(P.er.p, P.ep.p, rr[cur], rr[1 - cur], total, P.ldp, st);
+                cur = 1 - cur;
+            }
+        }
+        rhs = P.ACC.p;
+    }
+    if (mode == ApplyMode::Scale)
+        launch_scale_epilogue(P.ACC.p, epi.num, epi.out, epi.out_a, epi.a, epi.rec, phi, P.nfloor.p, P.n, P.ldp, st);
+}
+
+}  // namespace
+
+void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
+    if (P.kernel == GS_KERNEL_EULER)
+        enqueue_euler_apply(P, X, mode, epi, phi, st);
+    else
+        enqueue_cheb_apply(P, X, mode, epi, phi, st);
+}
+
 // Average duration (ms) of one step launch over `reps` whole applications of
 // p_K (accumulator form), and the average algorithmic bytes of a launch.
 double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch) {
     const LaunchShape saved = P.shape;
     P.shape = shape;
     if (!(shape == saved) || P.long_thr == 0) update_long_rows(P);
-    enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+    enqueue_cheb_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     hipEvent_t e0, e1;
     GS_HIP(hipEventCreate(&e0));
     GS_HIP(hipEventCreate(&e1));
     GS_HIP(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i) enqueue_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+    for (int i = 0; i < reps; ++i) enqueue_cheb_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
     GS_HIP(hipEventRecord(e1, st));
     GS_HIP(hipEventSynchronize(e1));
     if (!(shape == saved)) {

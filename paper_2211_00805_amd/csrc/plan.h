@@ -50,6 +50,13 @@ struct gs_plan_s {
     gs::DevBuf<float> segd, sege, dmu, dnu, vseed, wbar, wck, g4t;
     gs::DevBuf<double> tbar;
 
+    // kernel selection: GS_KERNEL_CHEBYSHEV or GS_KERNEL_EULER (N solves of
+    // cg_m conjugate-gradient iterations; cg_iters == 0 picks cg_m per call)
+    int kernel = GS_KERNEL_CHEBYSHEV;
+    int euler_N = 0, cg_iters = 0, cg_m = 0;
+    gs::DevBuf<float> er, ep, eq, ecoef;   // CG residual, direction, product; operator scale
+    gs::DevBuf<double> ers;                // per-column rr (two slots), p.qn, then column-pass partials
+
     std::map<std::string, hipGraphExec_t> graphs;
     std::map<std::string, hipGraph_t> graph_defs;
 
@@ -62,6 +69,8 @@ namespace gs {
 gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cache);
 void set_coefs(gs_plan_s& P, double lambda_hat, double t, hipStream_t st);
 void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st);
+void set_kernel(gs_plan_s& P, int kernel, int N, int cg_iters);
+int euler_cg_iterations(double t, int N);
 void heat_apply(gs_plan_s& P, double lam, double t, const float* X, float* Y, float* Ydt, hipStream_t st);
 void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J, float phi,
               int C, float* ckpt, float* v, float* w, double* dist, double* marg, int64_t* nfl, hipStream_t st);

@@ -88,6 +88,9 @@ def test_validation_rejects_before_any_device_call():
     assert lib.gs_sinkhorn(None, 2.0, 1.0, None, None, None, 1, 1e-30, 0, None, None, None, None, None, None,
                            None) == -1
     assert lib.gs_heat_apply(None, 2.0, 1.0, None, None, None, None) == -1
+    assert lib.gs_plan_set_kernel(None, 1, 4, 0) == -1
+    assert b"plan is NULL" in lib.gs_last_error()
+    assert lib.gs_expectation(None, None, 10, 1, None, None) == -1
 
 
 def test_abi_version():
