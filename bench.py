@@ -7,13 +7,16 @@ weights; heat kernel of degree K = 50 at t = 2; 256 histograms with support
 sizes log-uniform in [5k, 200k] (Dirichlet(1) weights on random nodes); the
 32,896 pairs i <= j of the 256 x 256 distance matrix are processed in batches
 of P pairs.  One step = Algorithm 1 for one batch of P pairs (J = 200
-iterations, checkpoints every 10) plus the hand-written reverse sweep giving
-d D / d mu, d D / d nu and d D / d t for every pair.
+iterations) plus the hand-written reverse sweep giving d D / d mu, d D / d nu
+and d D / d t for every pair.  By default the forward records every
+iteration's denominators in HBM (51 GB at this size) and the reverse sweep
+recomputes nothing; --ckpt-every C > 0 checkpoints w every C iterations
+instead and recomputes each segment.
 
 Reported value: heat-kernel applies/s over the timed steps, counting one
 single-RHS application per column per Chebyshev chain of the forward pass and
-of the adjoint sweep (B * (2J + 2J) per step); the recomputation of checkpoint
-segments is extra work, counted separately.  Also reported: the plain
+of the adjoint sweep (B * (2J + 2J) per step); recomputation of checkpoint
+segments (checkpoint mode only) is extra work, counted separately.  Also reported: the plain
 single-RHS form (B = 1) of the same fwd + bwd, the roofline of the fused
 Chebyshev step kernel (algorithmic bytes / its HIP-event duration), and the
 float64 oracle timed on the host on a bounded sample.
@@ -49,7 +52,8 @@ def parse():
     p.add_argument("--iters", type=int, default=200)
     p.add_argument("--K", type=int, default=50)
     p.add_argument("--t", type=float, default=2.0)
-    p.add_argument("--ckpt-every", type=int, default=10)
+    p.add_argument("--ckpt-every", type=int, default=-1,
+                   help="checkpoint interval C > 0, or -1: record every iteration (no recomputation)")
     p.add_argument("--per-cluster", type=int, default=20000, help="points per cluster (50 clusters)")
     p.add_argument("--knn", type=int, default=10)
     p.add_argument("--no-plain", action="store_true")
@@ -330,8 +334,8 @@ def main():
                           "plan": shape, "shape": shape_key(shape), "kernel_sha": kernel_source_hash(),
                           "n": n, "nnz": g.nnz, "B": P, "K": K}), flush=True)
         return
-    nseg = gs.n_checkpoints(J, ce)
-    ckpt = torch.empty(nseg * n * P, device=dev)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device=dev)
+    log(f"[setup] {'records' if ce == gs.GS_RECORD_ALL else 'checkpoints'}: {ckpt.numel() * 4 / 1e9:.1f} GB")
     gmu = torch.empty(n * P, device=dev)
     gnu = torch.empty(n * P, device=dev)
     ones = np.ones(P)
@@ -399,7 +403,7 @@ def main():
         plan1 = gs.Plan(g, K, 1, flags=gs.GS_PLAN_AUTOTUNE, tune_cache=TUNE_CACHE)
         mu1 = dev_batches[0][0][:, :1].contiguous()
         nu1 = dev_batches[0][1][:, :1].contiguous()
-        ck1 = torch.empty(nseg * n, device=dev)
+        ck1 = torch.empty(gs.ckpt_floats(plan1, J, ce), device=dev)
         g1m = torch.empty(n, device=dev)
 
         def step1():
@@ -437,11 +441,13 @@ def main():
                                 "%d pairs per step from the 256x256 pair matrix; forward + reverse sweep"
                                 % (args.per_cluster, args.knn, K, t, J, ce, P)),
                    "n": n, "nnz": g.nnz, "lambda_hat": round(lam, 6), "pairs_per_step": P, "K": K, "t": t,
-                   "iters": J, "ckpt_every": ce, "plan": shape},
+                   "iters": J, "ckpt_every": ce,
+                   "reverse_sweep": "recorded denominators" if ce == gs.GS_RECORD_ALL else f"checkpoints every {ce}",
+                   "plan": shape},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sinkhorn_iters_per_s": round(P * J / (ms_per_step / 1e3), 1),
-        "recompute_applies_per_step": P * 2 * J,
+        "recompute_applies_per_step": 0 if ce == gs.GS_RECORD_ALL else P * 2 * J,
         "step_kernel_gbs_algorithmic": round(achieved, 1),
         "copy_kernel_gbs": round(copy_gbs, 1),
         "plain_single_rhs": plain,

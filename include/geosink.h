@@ -197,6 +197,10 @@ void gs_plan_destroy(gs_plan p);
 gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, float* Y,
                         float* Ydt, hipStream_t stream);
 
+/* ckpt_every value of gs_sinkhorn / gs_sinkhorn_backward: record every
+ * iteration's denominators instead of checkpointing w. */
+#define GS_RECORD_ALL (-1)
+
 /* Algorithm 1 (Geodesic Sinkhorn) for B independent pairs (column b of mu, nu).
  *   a        device n vertex weights, or NULL for all ones.
  *   mu, nu   device n x B, finite, >= 0 (not renormalised).
@@ -204,7 +208,14 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
  *   phi      denominator floor (> 0, e.g. 1e-30): d = r if r > phi else phi.
  *   ckpt_every, ckpt   if ckpt != NULL, w^{s*C} (C = ckpt_every >= 1) is
  *            stored at ckpt + s*n*B for s = 0..ceil(J/C)-1 (device, caller
- *            sized ceil(J/C)*n*B floats), for gs_sinkhorn_backward.
+ *            sized ceil(J/C)*n*B floats), for gs_sinkhorn_backward.  With
+ *            ckpt_every = GS_RECORD_ALL, ckpt instead receives every
+ *            iteration's floored denominators d_j = floor(p_K(a w^j)) and
+ *            e_j = floor(p_K(a v^{j+1})) (slots 2j and 2j+1, each n x ldp with
+ *            ldp = B rounded up to a multiple of 4, 1 when B = 1; caller sized
+ *            2*J*n*ldp floats: 51 GB at n = 1M, B = 32, J = 200), so that the
+ *            reverse sweep recomputes nothing.  Captured graphs hold the
+ *            record buffer's address; a call with another buffer recaptures.
  *   v, w     device n x B outputs v^J, w^J (either may be NULL).
  *   dist     host B doubles: D = 4t sum_i a_i (mu_i ln v_i + nu_i ln w_i)
  *            (0 ln 0 = 0), the value on Algorithm 1's return line; NULL ok.
@@ -221,7 +232,9 @@ gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, co
 /* Gradient of sum_b grad_dist[b] * D_b with respect to mu, nu and t, through
  * exactly `iters` unrolled iterations of Algorithm 1 (d floor(r)/dr = 1[r>phi],
  * lambda_hat held fixed).  Iterates are recomputed segment by segment from
- * the checkpoints written by gs_sinkhorn with the same arguments; p_K is
+ * the checkpoints written by gs_sinkhorn with the same arguments (or, with
+ * ckpt_every = GS_RECORD_ALL, read from its records without recomputation;
+ * grad_mu and grad_nu are then bitwise those of the checkpointed sweep); p_K is
  * symmetric, so every adjoint is another Chebyshev application, with a second
  * accumulator (db_k/dt) for the gradient in t.
  *   grad_dist  host B doubles (the upstream gradient of each D_b).

@@ -14,10 +14,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GS_KERNEL_CHEBYSHEV, GS_KERNEL_EULER, GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GeoSinkError, check, lib
+from ._lib import (GS_KERNEL_CHEBYSHEV, GS_KERNEL_EULER, GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GS_RECORD_ALL,
+                   GeoSinkError, check, lib)
 
 __all__ = [
     "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "GS_KERNEL_CHEBYSHEV", "GS_KERNEL_EULER",
+    "GS_RECORD_ALL", "ckpt_floats",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
     "gs_barycenter", "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream",
@@ -191,6 +193,15 @@ def n_checkpoints(iters: int, ckpt_every: int) -> int:
     return (int(iters) + int(ckpt_every) - 1) // int(ckpt_every)
 
 
+def ckpt_floats(plan: Plan, iters: int, ckpt_every: int) -> int:
+    """Floats of the ckpt buffer: checkpoints of w (n x B each), or with
+    GS_RECORD_ALL the 2 * iters denominator records (n x ldp each)."""
+    if int(ckpt_every) == GS_RECORD_ALL:
+        ldp = 1 if plan.B == 1 else (plan.B + 3) // 4 * 4
+        return 2 * int(iters) * plan.n * ldp
+    return n_checkpoints(iters, ckpt_every) * plan.n * plan.B
+
+
 def gs_sinkhorn(plan: Plan, lambda_hat: float, t: float, mu: torch.Tensor, nu: torch.Tensor, iters: int,
                 phi: float = 1e-30, a: torch.Tensor | None = None, ckpt_every: int = 0,
                 ckpt: torch.Tensor | None = None, v: torch.Tensor | None = None, w: torch.Tensor | None = None,
@@ -202,7 +213,7 @@ def gs_sinkhorn(plan: Plan, lambda_hat: float, t: float, mu: torch.Tensor, nu: t
     marg = np.zeros(B, dtype=np.float64)
     nfl = C.c_int64(0)
     if ckpt is not None:
-        _dev(ckpt, "ckpt", n_checkpoints(iters, ckpt_every) * nb)
+        _dev(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
     check("gs_sinkhorn", lib.gs_sinkhorn(
         plan.handle, float(lambda_hat), float(t), _dev(a, "a", plan.n), _dev(mu, "mu", nb), _dev(nu, "nu", nb),
         int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"), _dev(v, "v", nb), _dev(w, "w", nb),
@@ -221,7 +232,7 @@ def gs_sinkhorn_backward(plan: Plan, lambda_hat: float, t: float, mu: torch.Tens
     nb = _nB(plan)
     gd = np.ascontiguousarray(np.broadcast_to(np.asarray(grad_dist, dtype=np.float64), (plan.B,)))
     gt = np.zeros(plan.B, dtype=np.float64)
-    _dev(ckpt, "ckpt", n_checkpoints(iters, ckpt_every) * nb)
+    _dev(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
     check("gs_sinkhorn_backward", lib.gs_sinkhorn_backward(
         plan.handle, float(lambda_hat), float(t), _dev(a, "a", plan.n), _dev(mu, "mu", nb), _dev(nu, "nu", nb),
         int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"), gd.ctypes.data_as(_lib.P_f64),

@@ -248,7 +248,8 @@ gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, co
         GS_REQUIRE(mu != nullptr && nu != nullptr, "mu / nu is NULL");
         GS_REQUIRE(iters >= 1, "iters must be >= 1");
         GS_REQUIRE(std::isfinite(phi) && phi > 0.f, "phi must be finite and > 0");
-        GS_REQUIRE(ckpt == nullptr || ckpt_every >= 1, "ckpt_every must be >= 1 when ckpt is given");
+        GS_REQUIRE(ckpt == nullptr || ckpt_every >= 1 || ckpt_every == GS_RECORD_ALL,
+                   "ckpt_every must be >= 1 or GS_RECORD_ALL when ckpt is given");
         sinkhorn(*p, lambda_hat, t, a, mu, nu, iters, phi, ckpt ? ckpt_every : 1, ckpt, v, w, dist, marg_err,
                  n_floored, stream);
     });
@@ -264,7 +265,8 @@ gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const flo
         GS_REQUIRE(t > 0.0, "t must be > 0 for the backward");
         GS_REQUIRE(mu != nullptr && nu != nullptr && ckpt != nullptr && grad_dist != nullptr,
                    "mu / nu / ckpt / grad_dist is NULL");
-        GS_REQUIRE(iters >= 1 && ckpt_every >= 1, "iters and ckpt_every must be >= 1");
+        GS_REQUIRE(iters >= 1 && (ckpt_every >= 1 || ckpt_every == GS_RECORD_ALL),
+                   "iters must be >= 1 and ckpt_every >= 1 or GS_RECORD_ALL");
         GS_REQUIRE(std::isfinite(phi) && phi > 0.f, "phi must be finite and > 0");
         for (int b = 0; b < p->B; ++b) GS_REQUIRE(std::isfinite(grad_dist[b]), "grad_dist must be finite");
         sinkhorn_backward(*p, lambda_hat, t, a, mu, nu, iters, phi, ckpt_every, ckpt, grad_dist, grad_mu, grad_nu,

@@ -493,6 +493,19 @@ ReduceArgs red_args(gs_plan_s& P, int op, const float* x0, const float* x1, cons
 
 }  // namespace
 
+namespace {
+
+// Captured record-mode graphs hold the record buffer's slot addresses: a call
+// with another buffer drops them.
+void use_record_buffer(gs_plan_s& P, const float* rec) {
+    if (P.rec_buf != rec) {
+        drop_graphs(P);
+        P.rec_buf = rec;
+    }
+}
+
+}  // namespace
+
 void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J, float phi,
               int C, float* ckpt, float* v, float* w, double* dist, double* marg, int64_t* nfl, hipStream_t st) {
     const bool has_a = a != nullptr;
@@ -502,10 +515,26 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
     if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
     GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
     const std::string key = std::string("fwd:") + (has_a ? "a" : "1") + phi_tag(phi);
-    for (int j = 0; j < J; ++j) {
-        if (ckpt && j % C == 0)
-            launch_copy_ld(P.w.p, P.ldp, ckpt + (size_t)(j / C) * P.n * P.B, P.B, P.n, P.B, st);
-        run_graph(P, key, st, [&](hipStream_t s) { enqueue_iteration(P, has_a, phi, nullptr, nullptr, s); });
+    if (ckpt && C == GS_RECORD_ALL) {
+        // every iteration's floored denominators d_j, e_j into slots 2j, 2j+1
+        // (graphs per chunk of iterations: the slot addresses are baked in)
+        use_record_buffer(P, ckpt);
+        const size_t sz = P.sz();
+        for (int j0 = 0; j0 < J; j0 += kRecordChunk) {
+            const int ns = std::min(kRecordChunk, J - j0);
+            run_graph(P, "fwdrec:" + std::to_string(j0) + ":" + std::to_string(ns) + ":" + key, st,
+                      [&](hipStream_t s) {
+                          for (int j = j0; j < j0 + ns; ++j)
+                              enqueue_iteration(P, has_a, phi, ckpt + 2 * (size_t)j * sz,
+                                                ckpt + (2 * (size_t)j + 1) * sz, s);
+                      });
+        }
+    } else {
+        for (int j = 0; j < J; ++j) {
+            if (ckpt && j % C == 0)
+                launch_copy_ld(P.w.p, P.ldp, ckpt + (size_t)(j / C) * P.n * P.B, P.B, P.n, P.B, st);
+            run_graph(P, key, st, [&](hipStream_t s) { enqueue_iteration(P, has_a, phi, nullptr, nullptr, s); });
+        }
     }
     const float* ap = has_a ? P.a.p : nullptr;
     if (dist) reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, dist, st);
@@ -551,10 +580,53 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
     GS_HIP(hipMemsetAsync(P.tbar.p, 0, P.ldp * sizeof(double), st));
     GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
     const float* ap = has_a ? P.a.p : nullptr;
-    const int nseg = (J + C - 1) / C;
     const int nblk = reduce_blocks(P.n);
     std::vector<double> D(P.B, 0.0);
 
+    // One reverse iteration j from its denominators d_j, e_j (w_j = nu / e_j,
+    // v_j = mu / d_j); e_prev = e_{j-1} or NULL for j = 0 (w^0 = 1), w_prev =
+    // the stored w^j instead of nu / e_{j-1} when given.
+    auto reverse_iteration = [&](const float* dj, const float* ej, const float* e_prev, const float* w_prev,
+                                 hipStream_t q) {
+        launch_bwd_e(P.wbar.p, ej, P.nu.p, P.n, P.ldp, phi, P.dnu.p, P.X.p, q);
+        enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
+        launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.mu.p, dj, nullptr, ap), P.partials.p, nblk, P.tbar.p, 1,
+                      1.0, q);
+        launch_bwd_d(P.ACC.p, P.vseed.p, dj, P.mu.p, ap, P.n, P.ldp, phi, P.dmu.p, P.X.p, q);
+        enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
+        if (e_prev)
+            launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.nu.p, e_prev, nullptr, ap), P.partials.p, nblk,
+                          P.tbar.p, 1, 1.0, q);
+        else
+            launch_reduce(red_args(P, RED_DOT, P.ACC2.p, w_prev, nullptr, nullptr, ap), P.partials.p, nblk, P.tbar.p,
+                          1, 1.0, q);
+        launch_bwd_w(P.ACC.p, ap, P.n, P.ldp, P.wbar.p, q);
+    };
+
+    if (C == GS_RECORD_ALL) {
+        // no recomputation: the forward recorded every d_j, e_j; the final
+        // v = mu / d_{J-1}, w = nu / e_{J-1} are rebuilt bitwise from them
+        use_record_buffer(P, ckpt);
+        const float* rec = ckpt;
+        launch_scale_epilogue(rec + 2 * (size_t)(J - 1) * sz, P.mu.p, P.v.p, nullptr, nullptr, nullptr, phi,
+                              P.nfloor.p, P.n, P.ldp, st);
+        launch_scale_epilogue(rec + (2 * (size_t)(J - 1) + 1) * sz, P.nu.p, P.w.p, nullptr, nullptr, nullptr, phi,
+                              P.nfloor.p, P.n, P.ldp, st);
+        reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
+        launch_bwd_seed(P.mu.p, P.nu.p, P.v.p, P.w.p, ap, P.g4t.p, P.n, P.ldp, P.dmu.p, P.dnu.p, P.vseed.p, P.wbar.p,
+                        st);
+        const std::string tag = std::string(has_a ? ":a" : ":1") + phi_tag(phi);
+        for (int j0 = ((J - 1) / kRecordChunk) * kRecordChunk; j0 >= 0; j0 -= kRecordChunk) {
+            const int ns = std::min(kRecordChunk, J - j0);
+            run_graph(P, "adjrec:" + std::to_string(j0) + ":" + std::to_string(ns) + tag, st, [&](hipStream_t q) {
+                for (int j = j0 + ns - 1; j >= j0; --j) {
+                    const float* dj = rec + 2 * (size_t)j * sz;
+                    reverse_iteration(dj, dj + sz, j > 0 ? dj - sz : nullptr, nullptr, q);
+                }
+            });
+        }
+    }
+    const int nseg = C == GS_RECORD_ALL ? 0 : (J + C - 1) / C;
     for (int s = nseg - 1; s >= 0; --s) {
         const int j0 = s * C;
         const int ns = std::min(J, j0 + C) - j0;
@@ -575,21 +647,7 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
             for (int slot = ns - 1; slot >= 0; --slot) {
                 const float* dj = P.segd.p + slot * sz;
                 const float* ej = P.sege.p + slot * sz;
-                // w_j = nu / e_j, e_j = floor(p_K(a v_j))
-                launch_bwd_e(P.wbar.p, ej, P.nu.p, P.n, P.ldp, phi, P.dnu.p, P.X.p, q);
-                enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
-                launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.mu.p, dj, nullptr, ap), P.partials.p, nblk,
-                              P.tbar.p, 1, 1.0, q);
-                // v_j = mu / d_j, d_j = floor(p_K(a w_{j-1}))
-                launch_bwd_d(P.ACC.p, P.vseed.p, dj, P.mu.p, ap, P.n, P.ldp, phi, P.dmu.p, P.X.p, q);
-                enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
-                if (slot > 0)
-                    launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.nu.p, ej - sz, nullptr, ap), P.partials.p,
-                                  nblk, P.tbar.p, 1, 1.0, q);
-                else
-                    launch_reduce(red_args(P, RED_DOT, P.ACC2.p, P.wck.p, nullptr, nullptr, ap), P.partials.p, nblk,
-                                  P.tbar.p, 1, 1.0, q);
-                launch_bwd_w(P.ACC.p, ap, P.n, P.ldp, P.wbar.p, q);
+                reverse_iteration(dj, ej, slot > 0 ? ej - sz : nullptr, P.wck.p, q);
             }
         });
     }

@@ -11,6 +11,8 @@ namespace gs {
 
 enum class ApplyMode { Store, Dual, Scale };
 
+constexpr int kRecordChunk = 8;   // iterations per captured graph in record mode
+
 struct StepSched {
     int flags;
     int cmask;
@@ -47,6 +49,7 @@ struct gs_plan_s {
     gs::DevBuf<float> bary;    // barycenter (n)
     // backward workspace (allocated on first use)
     int seg_cap = 0;
+    const float* rec_buf = nullptr;   // record buffer whose addresses the captured graphs hold
     gs::DevBuf<float> segd, sege, dmu, dnu, vseed, wbar, wck, g4t;
     gs::DevBuf<double> tbar;
 

@@ -1,0 +1,70 @@
+"""Record mode of Algorithm 1's reverse sweep (ckpt_every = GS_RECORD_ALL).
+
+The forward keeps every iteration's floored denominators, so the reverse
+sweep recomputes nothing.  Against the checkpointed sweep (which the oracle
+tests check): distances, v, w and floor counts are bitwise equal, the
+gradients in mu and nu bitwise equal, the gradient in t equal up to the
+rounding of the first reduction of each checkpoint segment (the
+checkpointed sweep reads the stored w there, the record sweep nu / e), for
+ragged and full widths, with and without vertex weights, with J not a
+multiple of the graph chunk or the checkpoint interval, and again on a
+second record buffer (captured graphs hold the buffer's address).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2211_00805_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def swiss():
+    X = synth.swiss_roll(2000, 10, 0.05, workload=1)
+    arrs, L, info, A = oracle_csr(X, 10)
+    return arrs, L
+
+
+def _run(gs, plan, lam, t, mu, nu, J, ce, a):
+    n, B = mu.shape
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    v = torch.empty(n * B, device="cuda")
+    w = torch.empty(n * B, device="cuda")
+    out = gs.gs_sinkhorn(plan, lam, t, mu, nu, J, a=a, ckpt_every=ce, ckpt=ckpt, v=v, w=w, want_floors=True)
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gd = np.linspace(0.5, 1.5, B)
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mu, nu, J, ce, ckpt, gd, a=a, grad_mu=gmu, grad_nu=gnu)
+    return out, v, w, gmu, gnu, gt
+
+
+@pytest.mark.parametrize("B", [3, 32])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_record_mode_equals_checkpointed_sweep(gs, swiss, B, weighted):
+    arrs, L = swiss
+    n, K, t, J = 2000, 20, 1.0, 21
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    rng = np.random.default_rng(B + 7 * weighted)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1)
+    a = to_dev(rng.uniform(0.5, 1.5, n).astype(np.float32)) if weighted else None
+    mud, nud = to_dev(mu), to_dev(nu)
+    plan = gs.Plan(g, K, B)
+    ref = _run(gs, plan, lam, t, mud, nud, J, 5, a)
+    for again in range(2):          # second pass: a new record buffer
+        rec = _run(gs, plan, lam, t, mud, nud, J, gs.GS_RECORD_ALL, a)
+        assert np.array_equal(rec[0]["dist"], ref[0]["dist"])
+        assert rec[0]["n_floored"] == ref[0]["n_floored"]
+        for i in (1, 2, 3, 4):
+            assert torch.equal(rec[i], ref[i]), (again, i)
+        np.testing.assert_allclose(rec[5], ref[5], rtol=1e-6, atol=1e-6 * np.abs(ref[5]).max())
