@@ -397,6 +397,36 @@ def main():
     copy_gbs = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
 
+    # gather reference: the rows the step kernel gathers (one 128-byte row of
+    # the n x 32 operand per nonzero, by the graph's own column indices), with
+    # nothing else in the kernel; and the same count by uniform random indices
+    gather_ref = None
+    if P == 32:
+        _, col, _, _ = g.export()
+        m = len(col)
+        idx_sets = {"csr_columns": torch.from_numpy(col.astype(np.int32)).to(dev),
+                    "uniform_random": torch.randint(0, n, (m,), dtype=torch.int32,
+                                                    generator=torch.Generator().manual_seed(11)).to(dev)}
+        Xop = dev_batches[0][0].view(n, 32)
+        gout = torch.empty((m + 31) // 32 * 32, device=dev)
+        gather_ref = {"rows_per_pass": m, "bytes_per_pass": m * 128}
+        for name, idx in idx_sets.items():
+            for _ in range(2):
+                gs.gs_stream_gather(Xop, idx, gout)
+            e0.record()
+            for _ in range(10):
+                gs.gs_stream_gather(Xop, idx, gout)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 10
+            gather_ref[name] = {"us": round(us, 1), "gbs": round(m * 128 / (us * 1e-6) / 1e9, 1)}
+        gather_ref["step_kernel_us"] = round(step_ms * 1e3, 1)
+        gather_ref["step_over_gather"] = round(step_ms * 1e3 / gather_ref["csr_columns"]["us"], 3)
+        log(f"[gather] csr columns {gather_ref['csr_columns']['us']:.1f} us "
+            f"({gather_ref['csr_columns']['gbs']:.0f} GB/s), random {gather_ref['uniform_random']['us']:.1f} us; "
+            f"step {step_ms * 1e3:.1f} us")
+        del idx_sets, gout
+
     # ---------------------------------------------------------------- plain single-RHS form
     plain = None
     if not args.no_plain:
@@ -450,6 +480,7 @@ def main():
         "recompute_applies_per_step": 0 if ce == gs.GS_RECORD_ALL else P * 2 * J,
         "step_kernel_gbs_algorithmic": round(achieved, 1),
         "copy_kernel_gbs": round(copy_gbs, 1),
+        "gather_reference": gather_ref,
         "plain_single_rhs": plain,
         "speedup_batched_vs_plain": round(value / plain["applies_per_s"], 2) if plain else None,
         "graph_build_s": round(t_graph, 2),

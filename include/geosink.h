@@ -292,6 +292,15 @@ gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double*
  * kernel; a bandwidth reference for the step kernel. */
 gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_t stream);
 
+/* Gather reference for the step kernel: for each run of 32 consecutive
+ * entries of idx (m entries), the sum of the 128-byte rows X[idx[e]] (X device
+ * n x 32 float32, node-major; an entry outside [0, n) reads row 0) is written
+ * to out (device, 32 * ceil(m / 32) floats).  With idx = a graph's CSR column
+ * array, one pass moves exactly the rows the step kernel gathers at B = 32,
+ * through the same load path, without the rest of the step.  Asynchronous. */
+gs_status gs_stream_gather(const float* X, int64_t n, const int32_t* idx, int64_t m, float* out,
+                           hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

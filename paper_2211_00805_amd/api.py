@@ -22,7 +22,7 @@ __all__ = [
     "GS_RECORD_ALL", "ckpt_floats",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
-    "gs_barycenter", "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "current_stream",
+    "gs_barycenter", "gs_expectation", "gs_plan_time_step", "gs_stream_copy", "gs_stream_gather", "current_stream",
 ]
 
 
@@ -284,3 +284,13 @@ def gs_stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
         raise ValueError("src and dst sizes differ")
     check("gs_stream_copy", lib.gs_stream_copy(_dev(src, "src"), _dev(dst, "dst"), src.numel(), current_stream()))
 
+
+def gs_stream_gather(X: torch.Tensor, idx: torch.Tensor, out: torch.Tensor) -> None:
+    """Sum runs of 32 gathered 128-byte rows X[idx] (X: (n, 32) float32, idx: int32) into out."""
+    if X.dim() != 2 or X.shape[1] != 32:
+        raise ValueError("X must be (n, 32)")
+    if idx.dtype != torch.int32 or idx.device.type != "cuda" or not idx.is_contiguous():
+        raise TypeError("idx must be a contiguous int32 device tensor")
+    m = idx.numel()
+    check("gs_stream_gather", lib.gs_stream_gather(_dev(X, "X"), X.shape[0], C.c_void_p(idx.data_ptr()), m,
+                                                   _dev(out, "out", (m + 31) // 32 * 32), current_stream()))

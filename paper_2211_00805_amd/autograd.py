@@ -1,8 +1,10 @@
 """Differentiable Geodesic Sinkhorn distance (torch.autograd.Function).
 
-Forward runs Algorithm 1 through gs_sinkhorn with iterate checkpoints; backward
-calls the library's hand-written reverse sweep gs_sinkhorn_backward, which
-recomputes each checkpoint segment and applies the adjoint Chebyshev
+Forward runs Algorithm 1 through gs_sinkhorn, recording every iteration's
+floored denominators (ckpt_every = GS_RECORD_ALL, 2 * iters * n * B floats)
+or checkpointing w every ckpt_every iterations; backward calls the library's
+hand-written reverse sweep gs_sinkhorn_backward, which reads the records (or
+recomputes each checkpoint segment) and applies the adjoint Chebyshev
 recurrence (p_K is symmetric, so the adjoint of an application is another
 application, with a second accumulator for the derivative in t).
 """
@@ -11,13 +13,13 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .api import Plan, gs_sinkhorn, gs_sinkhorn_backward, n_checkpoints
+from .api import GS_RECORD_ALL, Plan, ckpt_floats, gs_sinkhorn, gs_sinkhorn_backward
 
 
 class GeoSinkhornDistance(torch.autograd.Function):
     """D_b = 4t sum a (mu_b ln v_b + nu_b ln w_b) for the plan's B pairs.
 
-    apply(mu, nu, t, plan, lambda_hat, iters, ckpt_every=10, phi=1e-30, a=None)
+    apply(mu, nu, t, plan, lambda_hat, iters, ckpt_every=GS_RECORD_ALL, phi=1e-30, a=None)
       mu, nu: (n, B) float32 device tensors; t: float or 0-dim tensor.
     Returns a (B,) float64 tensor on mu's device.  Gradients flow to mu, nu
     (on their supports; zero elsewhere) and to t when it is a tensor that
@@ -25,13 +27,12 @@ class GeoSinkhornDistance(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, mu, nu, t, plan: Plan, lambda_hat: float, iters: int, ckpt_every: int = 10,
+    def forward(ctx, mu, nu, t, plan: Plan, lambda_hat: float, iters: int, ckpt_every: int = GS_RECORD_ALL,
                 phi: float = 1e-30, a=None):
         tval = float(t.detach().item()) if isinstance(t, torch.Tensor) else float(t)
         mu_c = mu.detach().contiguous()
         nu_c = nu.detach().contiguous()
-        ckpt = torch.empty(n_checkpoints(iters, ckpt_every) * plan.n * plan.B, device=mu.device,
-                           dtype=torch.float32)
+        ckpt = torch.empty(ckpt_floats(plan, iters, ckpt_every), device=mu.device, dtype=torch.float32)
         out = gs_sinkhorn(plan, lambda_hat, tval, mu_c, nu_c, iters, phi=phi, a=a, ckpt_every=ckpt_every,
                           ckpt=ckpt)
         ctx.save_for_backward(mu_c, nu_c, ckpt)
@@ -54,7 +55,7 @@ class GeoSinkhornDistance(torch.autograd.Function):
         return gmu, gnu, grad_t, None, None, None, None, None, None
 
 
-def geodesic_sinkhorn_distance(mu, nu, t, plan: Plan, lambda_hat: float, iters: int, ckpt_every: int = 10,
+def geodesic_sinkhorn_distance(mu, nu, t, plan: Plan, lambda_hat: float, iters: int, ckpt_every: int = GS_RECORD_ALL,
                                phi: float = 1e-30, a=None):
     """Functional form of GeoSinkhornDistance.apply."""
     return GeoSinkhornDistance.apply(mu, nu, t, plan, lambda_hat, iters, ckpt_every, phi, a)

@@ -335,4 +335,15 @@ gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_
     });
 }
 
+gs_status gs_stream_gather(const float* X, int64_t n, const int32_t* idx, int64_t m, float* out,
+                           hipStream_t stream) {
+    return guarded([&] {
+        GS_REQUIRE(X != nullptr && idx != nullptr && out != nullptr, "X / idx / out is NULL");
+        GS_REQUIRE(n >= 1 && m >= 0 && m < ((int64_t)1 << 40), "bad sizes");
+        if (m == 0) return;
+        launch_gather_rows(X, n, idx, m, out, stream);
+        GS_HIP(hipGetLastError());
+    });
+}
+
 }  // extern "C"

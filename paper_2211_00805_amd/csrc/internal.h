@@ -189,6 +189,10 @@ void launch_cg_dir(const float* r, float* p, const double* rr_old, const double*
 void launch_scale_epilogue(const float* acc, const float* num, float* out, float* out_a, const float* a, float* rec,
                            float phi, unsigned long long* nfloor, int64_t n, int ldp, hipStream_t st);
 
+// gather-throughput helper (measure.hip): out holds gather_out_floats(m) floats
+int64_t gather_out_floats(int64_t m);
+void launch_gather_rows(const float* X, int64_t n, const int32_t* idx, int64_t m, float* out, hipStream_t st);
+
 // kNN candidates (knn.hip): cand (n x kk) int32, candidate ids sorted by fp32 Gram distance
 void launch_knn_candidates(const float* Xc, const float* norms, int64_t n, int d, int kk, int32_t* cand,
                            hipStream_t st);

@@ -108,9 +108,11 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
-def test_autograd_function(gs, clusters):
+@pytest.mark.parametrize("ce", [5, -1])
+def test_autograd_function(gs, clusters, ce):
+    """Through torch.autograd, with checkpoints every 5 iterations and with records (-1)."""
     n, labels, arrs, L = clusters
-    B, K, J, ce = 2, 20, 10, 5
+    B, K, J = 2, 20, 10
     rng = np.random.default_rng(77)
     mu, nu = _grad_case(n, labels, B, rng)
     lam = lam_hat_of(L)
