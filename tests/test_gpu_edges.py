@@ -1,0 +1,130 @@
+"""Degenerate and extreme inputs of the GPU path.
+
+  * t = 0: p_K is the identity (b_0 = 2, every other coefficient 0), so the
+    heat application returns its input bit for bit and D = 0;
+  * an all-zero histogram column in a batch: v = 0 there, every e floors at
+    phi, D = 4t sum nu ln(nu / phi) (as in the oracle), other columns
+    unaffected;
+  * the largest degree, K = 256 at t = 100;
+  * the smallest graph, one edge: heat applications against the two-node
+    closed form, the Dirac-to-Dirac distance against -4t ln H_12 and against
+    the hand-derived golden values within the truncation bound;
+  * a wide batch, B = 1024 columns.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import closed_forms, heat, sinkhorn
+from gpu_common import heat_tol, lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_node.json")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2211_00805_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def swiss():
+    X = synth.swiss_roll(2000, 10, 0.05, workload=1)
+    arrs, L, info, A = oracle_csr(X, 10)
+    return arrs, L
+
+
+@pytest.mark.parametrize("B", [1, 7, 32])
+def test_time_zero_is_the_identity(gs, swiss, B):
+    arrs, L = swiss
+    n = 2000
+    g = gs.gs_graph_from_csr(n, *arrs)
+    x = to_dev(synth.random_dense_like(n, B, np.random.default_rng(B)))
+    plan = gs.Plan(g, 20, B)
+    Y = torch.empty(n * B, device="cuda")
+    gs.gs_heat_apply(plan, lam_hat_of(L), 0.0, x, Y)
+    assert torch.equal(Y, x.view(-1))
+    rng = np.random.default_rng(5)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 100, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 100, rng) for _ in range(B)], axis=1)
+    out = gs.gs_sinkhorn(plan, lam_hat_of(L), 0.0, to_dev(mu), to_dev(nu), 5)
+    assert np.all(out["dist"] == 0.0)
+
+
+def test_zero_histogram_column(gs, swiss):
+    arrs, L = swiss
+    n, K, t, J, B = 2000, 20, 1.0, 30, 4
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    rng = np.random.default_rng(9)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 300, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 300, rng) for _ in range(B)], axis=1)
+    mu[:, 2] = 0.0
+    ref = sinkhorn.sinkhorn(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, marginals=False)
+    nu64 = nu[:, 2].astype(np.float64)
+    s = nu64 > 0
+    closed = 4 * t * np.sum(nu64[s] * np.log(nu64[s] / 1e-30))
+    assert ref["D"][2] == pytest.approx(closed, rel=1e-12)
+    plan = gs.Plan(g, K, B)
+    out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, want_floors=True)
+    assert np.all(np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t))
+    assert out["n_floored"] == ref["n_floored"]
+
+
+def test_largest_degree(gs, swiss):
+    arrs, L = swiss
+    n, K, t, B = 2000, 256, 100.0, 4
+    lam = lam_hat_of(L)
+    assert heat.tail_bound(t, K) < 1e-30
+    g = gs.gs_graph_from_csr(n, *arrs)
+    x = synth.random_dense_like(n, B, np.random.default_rng(3))
+    plan = gs.Plan(g, K, B)
+    Y = torch.empty(n * B, device="cuda")
+    gs.gs_heat_apply(plan, lam, t, to_dev(x), Y)
+    ref = heat.heat_apply(L, lam, t, K, x.astype(np.float64))
+    assert np.abs(to_host(Y).reshape(n, B) - ref).max() <= heat_tol(K, np.abs(x).max())
+
+
+@pytest.mark.parametrize("t", [0.5, 1.0, 2.0])
+def test_one_edge_graph(gs, t):
+    K = 30
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([1, 0], dtype=np.int32)
+    w = np.array([1.0, 1.0], dtype=np.float32)
+    g = gs.gs_graph_from_csr(2, rp, col, w)
+    H = closed_forms.two_node_kernel(t, K)
+    for B in (1, 4):
+        x = synth.random_dense_like(2, B, np.random.default_rng(B))
+        plan = gs.Plan(g, K, B)
+        Y = torch.empty(2 * B, device="cuda")
+        gs.gs_heat_apply(plan, 2.0, t, to_dev(x), Y)
+        assert np.abs(to_host(Y).reshape(2, B) - H @ x.astype(np.float64)).max() <= heat_tol(K, np.abs(x).max())
+    plan = gs.Plan(g, K, 1)
+    mu = np.array([[1.0], [0.0]], dtype=np.float32)
+    nu = np.array([[0.0], [1.0]], dtype=np.float32)
+    D = gs.gs_sinkhorn(plan, 2.0, t, to_dev(mu), to_dev(nu), 3)["dist"][0]
+    ref = closed_forms.two_node_dirac_distance(t, K)
+    assert abs(D - ref) <= 1e-5 * max(abs(ref), 4 * t)
+    gold = json.load(open(GOLDEN))["D_exact"][repr(t)]
+    # truncation: |p_K - exp| <= tail on each entry; D = -4t ln H_12
+    assert abs(D - gold) <= 1e-5 * max(abs(gold), 4 * t) + 4 * t * heat.tail_bound(t, K) / H[0, 1]
+
+
+def test_wide_batch(gs, swiss):
+    arrs, L = swiss
+    n, K, t, B = 2000, 8, 1.0, 1024
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    x = synth.random_dense_like(n, B, np.random.default_rng(12))
+    plan = gs.Plan(g, K, B)
+    Y = torch.empty(n * B, device="cuda")
+    gs.gs_heat_apply(plan, lam, t, to_dev(x), Y)
+    cols = [0, 1, 511, 1000, 1023]
+    ref = heat.heat_apply(L, lam, t, K, x[:, cols].astype(np.float64))
+    assert np.abs(to_host(Y).reshape(n, B)[:, cols] - ref).max() <= heat_tol(K, np.abs(x).max())
