@@ -151,8 +151,10 @@ gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const 
 /* Override the launch shape of the fused Chebyshev step (tuning studies,
  * tests).  vec = 1 (float lanes, only when B == 1) or 4 (float4 lanes);
  * S lanes split each row's nonzeros (power of two), C lanes span column
- * groups of vec floats (power of two), S*C <= 64, and the padded B must be a
- * multiple of vec*C.  Cached hipGraphs of the plan are dropped. */
+ * groups of vec floats (power of two), S*C <= 64; a row takes
+ * ceil(padded B / (vec*C)) column tiles, lanes past the padded row idle, and
+ * C must be 1 or below twice the number of float4 groups (padded B / 4).
+ * Cached hipGraphs of the plan are dropped. */
 gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C);
 
 /* Kernel a plan applies in gs_heat_apply, gs_sinkhorn and gs_barycenter. */

@@ -188,7 +188,7 @@ gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
         const LaunchShape s{vec, S, C, p->shape.remap};
         GS_REQUIRE(shape_supported(s), "unsupported launch shape");
         GS_REQUIRE((vec == 1) == (p->ldp == 1), "vec must be 1 exactly when B == 1");
-        GS_REQUIRE(p->ldp % (vec * C) == 0, "padded B must be a multiple of vec*C");
+        GS_REQUIRE(column_lanes_ok(p->ldp, vec, C), "C must be 1 or below twice the padded B's float4 groups");
         GS_HIP(hipDeviceSynchronize());
         drop_graphs(*p);
         p->shape = s;

@@ -118,6 +118,9 @@ struct LaunchShape {
 };
 
 bool shape_supported(const LaunchShape& s);
+// C column lanes of vec floats over a padded row of ldp floats: a row takes
+// ceil(ldp / (vec C)) column tiles; lanes past the row stay idle
+bool column_lanes_ok(int ldp, int vec, int C);
 int long_row_threshold(const LaunchShape& s);
 std::vector<LaunchShape> candidate_shapes(int ldp);
 void launch_step(const LaunchShape& shape, const StepArgs& a, hipStream_t st);

@@ -204,10 +204,11 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     const int li = item / ncoltiles;
     const int row = A.long_rows[li];
     const int colofs = (item - li * ncoltiles) * (VEC * C) + c * VEC;
-    const size_t off = (size_t)row * A.ldp + colofs;
+    const bool colok = colofs < A.ldp;   // lanes past the padded row stay idle
+    const size_t off = (size_t)row * A.ldp + (colok ? colofs : 0);
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
-    if (s == 0) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
-    const int rs = A.rowptr[row], re = A.rowptr[row + 1];
+    if (s == 0 && colok) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
+    const int rs = A.rowptr[row], re = colok ? A.rowptr[row + 1] : rs;
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
     float sw = 0.f;
@@ -241,7 +242,7 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
         red[wave][c][VEC] = sw;
     }
     __syncthreads();
-    if (tid < C) {
+    if (tid < C && colok) {
 #pragma unroll
         for (int wv = 1; wv < 4; ++wv) {
 #pragma unroll
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ldp = A.ldp;
-    const int ncoltiles = ldp / (VEC * C);
+    const int ncoltiles = (ldp + VEC * C - 1) / (VEC * C);
     // the first blocks take the long rows (dispatched first, they overlap the tiles)
     const int nlb = A.nlong * ncoltiles;
     if ((int)blockIdx.x < nlb) {
@@ -278,9 +279,10 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int r0 = rt * RPB;
     const int r1 = r0 + RPB < A.n ? r0 + RPB : A.n;
     const int row = r0 + wave * RPW + lane / LPR;
-    const bool valid = row < A.n;
     const int colofs = ct * (VEC * C) + c * VEC;
-    const size_t off = (size_t)(valid ? row : r0) * ldp + colofs;
+    // lanes past the last row or the padded row stay idle but join the shuffles
+    const bool valid = row < A.n && colofs < ldp;
+    const size_t off = (size_t)(valid ? row : r0) * ldp + (colofs < ldp ? colofs : 0);
 
     const int eb = A.rowptr[r0];
     const int ee = A.rowptr[r1];
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
 
     Vec<VEC> sx = vzero<VEC>();
     float sw = 0.f;
-    const float* __restrict__ xrow = A.tprev + colofs;
+    const float* __restrict__ xrow = A.tprev + (colofs < ldp ? colofs : 0);
     const int self = valid ? row : r0;
     for (int cb = eb; cb < ee; cb += kChunk) {
         const int cend = cb + kChunk < ee ? cb + kChunk : ee;
@@ -350,7 +352,7 @@ template <int VEC, int S, int C>
 void launch_shape(const StepArgs& a, hipStream_t st) {
     constexpr int RPB = 4 * (64 / (S * C));
     const int nrt = (a.n + RPB - 1) / RPB;
-    const int nct = a.ldp / (VEC * C);
+    const int nct = (a.ldp + VEC * C - 1) / (VEC * C);
     const int grid = nrt * nct + a.nlong * nct;
     if (a.flags & STEP_DUAL)
         hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, true>), dim3(grid), dim3(kBlock), 0, st, a);
@@ -592,6 +594,11 @@ bool shape_supported(const LaunchShape& s) {
     return pow2S && pow2C && lpr <= 64;
 }
 
+bool column_lanes_ok(int ldp, int vec, int C) {
+    if (vec == 1) return C == 1;
+    return C == 1 || C / 2 < ldp / 4;   // some tile keeps more than half its column lanes busy
+}
+
 int long_row_threshold(const LaunchShape& s) {
     const int t = 32 * kUnroll * s.S;   // rows needing more than 32 gather batches per lane
     return t < 256 ? 256 : t;
@@ -605,7 +612,7 @@ std::vector<LaunchShape> candidate_shapes(int ldp) {
             continue;
         }
         for (int C : {1, 2, 4, 8, 16, 32, 64}) {
-            if ((ldp % (4 * C)) != 0) continue;
+            if (!column_lanes_ok(ldp, 4, C)) continue;
             for (int S : {1, 2, 4, 8, 16}) {
                 LaunchShape s{4, S, C, remap};
                 if (shape_supported(s)) out.push_back(s);

@@ -42,10 +42,13 @@ StepArgs base_args(gs_plan_s& P) {
     return a;
 }
 
+// Column lanes: the smallest power of two covering the row's float4 groups
+// (at most 16; a short last tile or idle lanes when the groups are not a
+// power of two), and S = 8 / C lanes over a row's nonzeros.
 LaunchShape default_shape(int ldp, double nnz_per_row) {
     if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1};
     int C = 1;
-    while (C * 2 <= 16 && (ldp % (4 * C * 2)) == 0) C *= 2;
+    while (C < 16 && C < ldp / 4) C *= 2;
     int S = std::max(1, 8 / C);
     return {4, S, C, 1};
 }
@@ -403,7 +406,7 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
         const auto hit = cache.find(key);
         int vv = 0, ss = 0, cc = 0, rr = 1;
         if (hit != cache.end() && std::sscanf(hit->second.c_str(), "%d,%d,%d,%d", &vv, &ss, &cc, &rr) == 4 &&
-            shape_supported({vv, ss, cc, rr}) && (P->ldp % (vv * cc)) == 0 && (vv == 1) == (P->ldp == 1)) {
+            shape_supported({vv, ss, cc, rr}) && column_lanes_ok(P->ldp, vv, cc) && (vv == 1) == (P->ldp == 1)) {
             P->shape = {vv, ss, cc, rr};
             P->shape_origin = "cache";
         } else {
