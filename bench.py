@@ -328,8 +328,23 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(3):
             gs.gs_stream_copy(src, dst)
+        del src, dst
+        gather_us = None
+        if P == 32:   # the step kernel's gathers alone (one 128-byte row per nonzero), 3 passes
+            _, col, _, _ = g.export()
+            idx = torch.from_numpy(col.astype(np.int32)).to(dev)
+            gout = torch.empty((len(col) + 31) // 32 * 32, device=dev)
+            Xop = dev_batches[0][0].view(n, 32)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(3):
+                gs.gs_stream_gather(Xop, idx, gout)
+            ev1.record()
+            torch.cuda.synchronize()
+            gather_us = ev0.elapsed_time(ev1) * 1e3 / 3
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "2 applications (K step launches each) + copy of 1 GiB x3", "step_ms": step_ms,
+        print(json.dumps({"probe": "2 applications (K step launches each) + copy of 1 GiB x3 + 3 gather passes",
+                          "step_ms": step_ms, "gather_us": gather_us,
                           "step_algorithmic_bytes": step_bytes, "copy_bytes_read": nb, "copy_bytes_written": nb,
                           "plan": shape, "shape": shape_key(shape), "kernel_sha": kernel_source_hash(),
                           "n": n, "nnz": g.nnz, "B": P, "K": K}), flush=True)
