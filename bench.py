@@ -123,7 +123,8 @@ def cpu_baseline(nnz_target: int, n: int, K: int, t: float):
     applies = B * (2 * J + 2 * J)
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": applies / dt, "unit": "heat-kernel applies/s", "cores": 1, "kind": "oracle",
-            "sample": (f"float64 oracle (scipy CSR products, single thread; host has {ncores} cores): "
+            "sample": (f"float64 oracle (scipy CSR products, single thread; host affinity {ncores} cores, "
+                       f"os.cpu_count() {os.cpu_count()}): "
                        f"1 Sinkhorn iteration forward + reverse sweep for {B} pairs, K={K}, t={t}, on a "
                        f"synthetic banded graph with n={n}, nnz={int(arrs[1].shape[0])} (workload nnz "
                        f"{nnz_target}); {applies} applies in {dt:.1f} s")}
@@ -411,6 +412,9 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
+    roofline["frac_of_copy_peak"] = round(achieved / copy_gbs, 4)
+    if traffic:
+        roofline["traffic_gbs"] = round(traffic / (step_ms * 1e-3) / 1e9, 1)
 
     # gather reference: the rows the step kernel gathers (one 128-byte row of
     # the n x 32 operand per nonzero, by the graph's own column indices), with
