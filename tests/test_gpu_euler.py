@@ -96,6 +96,25 @@ def test_euler_sinkhorn_and_barycenter_match_oracle(gs, swiss):
     assert np.abs(to_host(bary) - pref).sum() <= 1e-6
 
 
+def test_euler_sinkhorn_with_vertex_weights(gs, swiss):
+    """Vertex weights a go through the scaling epilogue (out_a = a out) of the Euler form."""
+    arrs, L = swiss
+    n, N, t, J, B = 2000, 3, 0.8, 40, 2
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    rng = np.random.default_rng(17)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 250, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 250, rng) for _ in range(B)], axis=1)
+    E = lambda v: heat.euler_apply(L, lam, t, N, v)
+    ref = sinkhorn.sinkhorn(L, lam, t, 0, mu.astype(np.float64), nu.astype(np.float64), J,
+                            a=a.astype(np.float64), apply=E, marginals=False)
+    plan = gs.Plan(g, 4, B)
+    plan.set_kernel(gs.GS_KERNEL_EULER, N)
+    out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(a))
+    assert np.all(np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t))
+
+
 def test_euler_graph_replay_and_switch_back(gs, swiss):
     arrs, L = swiss
     n, B = 2000, 8
