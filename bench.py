@@ -136,6 +136,9 @@ def extra_workloads(gs, synth, np, torch, dev):
     barycenter: n ~ 200k (30 clusters x 6667 on a curve in R^50, k = 15), m = 64
       inputs with log-uniform [1k, 50k] supports and Dirichlet(0.5) weights,
       alpha = 1/64, K = 40, t = 2, J = 300, all inputs in one multi-RHS launch.
+    gradient: the same graph, 32 pairs of Dirichlet(1) histograms on adjacent
+      blocks of 3 clusters (~20k nodes each, random start), K = 30, t = 2,
+      J = 200: forward with records + reverse sweep (mu, nu and t).
     plain_forward: n = 100k (20 clusters x 5000, R^50, k = 15), one pair with
       Dirichlet(1) on clusters 0-3 vs 4-7, K = 30, J = 500, t in {0.5, 2, 8}.
     swiss_roll: n = 2000 Swiss roll in R^10, k = 10, K = 20, t = 1, uniform
@@ -151,7 +154,7 @@ def extra_workloads(gs, synth, np, torch, dev):
     """
     out = {}
     # barycenter
-    X, _ = synth.clusters_on_curve(30, 6667, dim=50, sigma=0.1, workload=3)
+    X, labels3 = synth.clusters_on_curve(30, 6667, dim=50, sigma=0.1, workload=3)
     g = gs.gs_graph_from_points(X, 15)
     lam = gs.gs_lambda_max(g, iters=60, seed=3, safety=1.01)
     m, K, t, J = 64, 40, 2.0, 300
@@ -171,7 +174,35 @@ def extra_workloads(gs, synth, np, torch, dev):
                          "iterations_per_s": round(J / dt, 1), "applies_per_s": round(2 * m * J / dt, 1),
                          "plan": plan.describe(), "mass": round(float(bary.sum().item()), 6)}
     log(f"[extra] barycenter {dt:.2f}s")
-    del plan, g, Hd
+    del plan, Hd
+    # differentiation on the same graph: 32 pairs on adjacent blocks of 3 clusters (~20k nodes), K = 30,
+    # t = 2, J = 200, forward recording every iteration + reverse sweep (gradients in mu, nu and t)
+    B4, K4, J4 = 32, 30, 200
+    rng = np.random.default_rng(synth.seed_for(4, 2))
+    pairs = [synth.cluster_block_pair(labels3, int(rng.integers(0, 24)), 3, 1.0, rng) for _ in range(B4)]
+    mu4 = torch.from_numpy(np.stack([p_[0] for p_ in pairs], axis=1)).to(dev)
+    nu4 = torch.from_numpy(np.stack([p_[1] for p_ in pairs], axis=1)).to(dev)
+    plan4 = gs.Plan(g, K4, B4, flags=gs.GS_PLAN_AUTOTUNE)
+    rec4 = torch.empty(gs.ckpt_floats(plan4, J4, gs.GS_RECORD_ALL), device=dev)
+    gmu4 = torch.empty(g.n * B4, device=dev)
+    gnu4 = torch.empty(g.n * B4, device=dev)
+
+    def grad_step(J_):
+        gs.gs_sinkhorn(plan4, lam, 2.0, mu4, nu4, J_, ckpt_every=gs.GS_RECORD_ALL, ckpt=rec4)
+        return gs.gs_sinkhorn_backward(plan4, lam, 2.0, mu4, nu4, J_, gs.GS_RECORD_ALL, rec4, np.ones(B4),
+                                       grad_mu=gmu4, grad_nu=gnu4)
+
+    grad_step(2)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    gt4 = grad_step(J4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - w0
+    out["gradient"] = {"n": g.n, "nnz": g.nnz, "pairs": B4, "K": K4, "iters": J4, "seconds": round(dt, 3),
+                       "applies_per_s": round(4 * J4 * B4 / dt, 1), "plan": plan4.describe(),
+                       "grad_t_finite": bool(np.all(np.isfinite(gt4)))}
+    log(f"[extra] gradient fwd+bwd {dt:.2f}s")
+    del plan4, rec4, gmu4, gnu4, g
     # plain forward on the cluster-curve graph
     X, labels = synth.clusters_on_curve(20, 5000, dim=50, sigma=0.1, workload=2)
     g = gs.gs_graph_from_points(X, 15)
@@ -486,9 +517,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": ("50 Gaussian clusters x %d on a 2-D spline surface in R^100, sigma 0.1; "
-                                "symmetrised k=%d kNN; K=%d, t=%g; J=%d Sinkhorn iterations, checkpoints every %d; "
-                                "%d pairs per step from the 256x256 pair matrix; forward + reverse sweep"
-                                % (args.per_cluster, args.knn, K, t, J, ce, P)),
+                                "symmetrised k=%d kNN; K=%d, t=%g; J=%d Sinkhorn iterations; "
+                                "%d pairs per step from the 256x256 pair matrix; forward + reverse sweep (%s)"
+                                % (args.per_cluster, args.knn, K, t, J, P,
+                                   "from recorded denominators" if ce == gs.GS_RECORD_ALL
+                                   else f"checkpoints every {ce}, segments recomputed")),
                    "n": n, "nnz": g.nnz, "lambda_hat": round(lam, 6), "pairs_per_step": P, "K": K, "t": t,
                    "iters": J, "ckpt_every": ce,
                    "reverse_sweep": "recorded denominators" if ce == gs.GS_RECORD_ALL else f"checkpoints every {ce}",

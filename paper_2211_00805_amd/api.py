@@ -43,6 +43,13 @@ def _dev(t: torch.Tensor | None, name: str, numel: int | None = None):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev_min(t: torch.Tensor, name: str, numel: int):
+    """As _dev, for buffers that may be larger than needed (checkpoints, records)."""
+    if t is not None and isinstance(t, torch.Tensor) and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+    return _dev(t, name)
+
+
 def gs_abi_version() -> int:
     return int(lib.gs_abi_version())
 
@@ -213,7 +220,7 @@ def gs_sinkhorn(plan: Plan, lambda_hat: float, t: float, mu: torch.Tensor, nu: t
     marg = np.zeros(B, dtype=np.float64)
     nfl = C.c_int64(0)
     if ckpt is not None:
-        _dev(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
+        _dev_min(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
     check("gs_sinkhorn", lib.gs_sinkhorn(
         plan.handle, float(lambda_hat), float(t), _dev(a, "a", plan.n), _dev(mu, "mu", nb), _dev(nu, "nu", nb),
         int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"), _dev(v, "v", nb), _dev(w, "w", nb),
@@ -232,7 +239,7 @@ def gs_sinkhorn_backward(plan: Plan, lambda_hat: float, t: float, mu: torch.Tens
     nb = _nB(plan)
     gd = np.ascontiguousarray(np.broadcast_to(np.asarray(grad_dist, dtype=np.float64), (plan.B,)))
     gt = np.zeros(plan.B, dtype=np.float64)
-    _dev(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
+    _dev_min(ckpt, "ckpt", ckpt_floats(plan, iters, ckpt_every))
     check("gs_sinkhorn_backward", lib.gs_sinkhorn_backward(
         plan.handle, float(lambda_hat), float(t), _dev(a, "a", plan.n), _dev(mu, "mu", nb), _dev(nu, "nu", nb),
         int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"), gd.ctypes.data_as(_lib.P_f64),
