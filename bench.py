@@ -302,8 +302,9 @@ def extra_workloads(gs, synth, np, torch, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the method's multi-GPU sharding by "
-              "pairs is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): only the one-GPU path is built; "
+              "the method would shard by pairs (each GPU a share of the pair batches on a full graph replica, "
+              "one all-reduce of the histogram gradients at the end).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
