@@ -94,7 +94,7 @@ struct StepArgs {
     int32_t flags;
     int32_t cmask;        // terms added to the accumulator: 1 T_{k-2}, 2 T_{k-1}, 4 T_k
     int32_t remap;        // 1: give each XCD a contiguous range of row tiles
-    int32_t long_thr;     // rows with more nonzeros go to the long-row kernel (0: none)
+    int32_t long_thr;     // rows with more nonzeros go to the long-row blocks (0: none)
     int32_t nlong;        // number of such rows
     const int32_t* long_rows;
     // scaling epilogue

@@ -13,12 +13,13 @@
 // K4  bary_row:    barycenter update p = exp(sum alpha ln q), w = p / q.
 // K5  bwd_*:       elementwise adjoints of Algorithm 1's updates.
 //
-// The step kernel is bandwidth bound; its launch shape (lanes splitting a
-// row's nonzeros S, lanes across column groups C, float or float4 lanes) is
-// a template parameter chosen per plan, and the 1-D grid is remapped so that
-// each of the 8 XCDs (which receive blocks round-robin) walks a contiguous
-// range of rows, keeping the gathered rows of neighbouring nodes in that
-// XCD's L2.
+// The step kernel is bound by its gathers (one row of T_{k-1} per nonzero);
+// its launch shape (lanes splitting a row's nonzeros S, lanes across column
+// groups C, float or float4 lanes) is a template parameter chosen per plan,
+// lanes past a padded row stay idle, rows with very many nonzeros are taken
+// by the first blocks of the same grid (one block per row), and the 1-D grid
+// can be remapped (an autotuned choice) so that each of the 8 XCDs, which
+// receive blocks round-robin, walks a contiguous range of rows.
 #include <cfloat>
 #include <cmath>
 
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         re = A.rowptr[row + 1];
         longrow = A.long_thr > 0 && re - rs > A.long_thr;
         if (longrow) {
-            re = rs;   // done by cheb_long_kernel
+            re = rs;   // taken by a long-row block at the head of the grid
         } else {
             load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
         }

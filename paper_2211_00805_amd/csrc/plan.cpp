@@ -169,7 +169,8 @@ gs_plan_s::~gs_plan_s() {
 namespace gs {
 
 // Rows whose nonzeros exceed the shape's threshold are processed one block per
-// row by the long-row kernel (a single row group would serialise them).
+// row by the long-row blocks at the head of the step grid (a single row group
+// would serialise them).
 void update_long_rows(gs_plan_s& P) {
     const int thr = long_row_threshold(P.shape);
     std::vector<int32_t> rows;

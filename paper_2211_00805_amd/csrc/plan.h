@@ -41,7 +41,7 @@ struct gs_plan_s {
     // Sinkhorn state (n x ldp) and vertex weights (n)
     gs::DevBuf<float> mu, nu, v, w, xv, xw, a;
     gs::DevBuf<float> coef;
-    gs::DevBuf<int32_t> long_rows;  // rows handled by the long-row kernel for the current shape
+    gs::DevBuf<int32_t> long_rows;  // rows handled by the long-row blocks for the current shape
     int nlong = 0, long_thr = 0;
     gs::DevBuf<double> partials, red;
     gs::DevBuf<unsigned long long> nfloor;
