@@ -224,7 +224,8 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
  *   marg_err host B doubles or NULL: ||a v p_K(a w) - a mu||_1 (one extra
  *            heat application per call).
  *   n_floored host int64 or NULL: count of floored denominators on the
- *            numerators' supports over all iterations.
+ *            numerators' supports over all iterations (NULL: not counted,
+ *            which saves the atomic updates when floors are frequent).
  * Synchronises `stream` when any host output is requested. */
 gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, const float* mu,
                       const float* nu, int32_t iters, float phi, int32_t ckpt_every, float* ckpt,
@@ -258,7 +259,7 @@ gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const flo
  *   bary     device n output p.  v, w: device n x m outputs or NULL.
  *   marg_err host m doubles or NULL: ||a v_i p_K(a w_i) - a mu_i||_1.
  *   n_floored host int64 or NULL: floored denominators (on mu_i's support
- *            for the v update, everywhere for q). */
+ *            for the v update, everywhere for q; NULL: not counted). */
 gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, const float* mus,
                         const double* alpha, int32_t iters, float phi, float* bary, float* v,
                         float* w, double* marg_err, int64_t* n_floored, hipStream_t stream);

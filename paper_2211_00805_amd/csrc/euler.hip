@@ -129,7 +129,8 @@ __global__ void cg_dir_kernel(const float* r, float* p, const double* rr_old, co
 
 // Algorithm 1's scaling after a kernel application held in acc, with the
 // step epilogue's floor rule: d = acc if acc > phi else phi, out = num / d,
-// out_a = a out, rec = d; floors counted where num > 0 (one atomic per wave).
+// out_a = a out, rec = d; floors counted where num > 0 when nfloor is given
+// (one atomic per wave; the grid is capped so a thread walks several elements).
 __global__ __launch_bounds__(kBlock) void scale_epilogue_kernel(const float* acc, const float* num, float* out,
                                                                 float* out_a, const float* a, float* rec, float phi,
                                                                 unsigned long long* nfloor, int64_t n, int ldp) {
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void scale_epilogue_kernel(const float* acc
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nfloor, (unsigned long long)cnt);
+    if (nfloor && (threadIdx.x & 63) == 0 && cnt) atomicAdd(nfloor, (unsigned long long)cnt);
 }
 
 
@@ -203,8 +204,9 @@ void launch_cg_dir(const float* r, float* p, const double* rr_old, const double*
 
 void launch_scale_epilogue(const float* acc, const float* num, float* out, float* out_a, const float* a, float* rec,
                            float phi, unsigned long long* nfloor, int64_t n, int ldp, hipStream_t st) {
-    hipLaunchKernelGGL(scale_epilogue_kernel, dim3(grid_for(n * (int64_t)ldp)), dim3(kBlock), 0, st, acc, num, out,
-                       out_a, a, rec, phi, nfloor, n, ldp);
+    const int grid = grid_for(n * (int64_t)ldp) < 1024 ? grid_for(n * (int64_t)ldp) : 1024;
+    hipLaunchKernelGGL(scale_epilogue_kernel, dim3(grid), dim3(kBlock), 0, st, acc, num, out, out_a, a, rec, phi,
+                       nfloor, n, ldp);
 }
 
 }  // namespace gs

@@ -163,7 +163,7 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t
         const float ai = A.a ? A.a[row] : 1.f;
         const float phi = A.phi;
         Vec<VEC> dd, o, oa;
-        unsigned cnt = 0;
+        bool fl[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const float r = accn.v[i];
@@ -171,12 +171,20 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t
             dd.v[i] = ok ? r : phi;
             o.v[i] = nm.v[i] / dd.v[i];
             oa.v[i] = ai * o.v[i];
-            cnt += (!ok && nm.v[i] > 0.f) ? 1u : 0u;
+            fl[i] = !ok && nm.v[i] > 0.f;
         }
         vstore<VEC>(A.out + off, o);
         if (A.out_a) vstore<VEC>(A.out_a + off, oa);
         if (A.rec) vstore<VEC>(A.rec + off, dd);
-        if (cnt) atomicAdd(A.nfloor, (unsigned long long)cnt);
+        if (A.nfloor) {
+            // floors on the numerator's support, one atomic per wave (the
+            // lanes here can be any subset of the wave: ballots count them)
+            unsigned long long cnt = 0;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) cnt += __popcll(__ballot(fl[i]));
+            const int leader = __ffsll((long long)__ballot(1)) - 1;
+            if (cnt && (int)(threadIdx.x & 63) == leader) atomicAdd(A.nfloor, cnt);
+        }
     } else if (flags & STEP_ACC_WRITE) {
         vstore_nt<VEC>(A.acc + off, accn);
         if constexpr (DUAL) vstore_nt<VEC>(A.acc2 + off, acc2n);
@@ -480,7 +488,10 @@ __global__ __launch_bounds__(kBlock) void bary_row_kernel(const float* acc, cons
         ls += (double)alpha[s] * log((double)q);
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o, 64);
+    for (int o = 32; o >= 1; o >>= 1) {
+        ls += __shfl_xor(ls, o, 64);
+        cnt += __shfl_xor(cnt, o, 64);
+    }
     const double p = exp(ls);
     const float ai = a ? a[row] : 1.f;
     for (int s = lane; s < m; s += 64) {
@@ -490,8 +501,10 @@ __global__ __launch_bounds__(kBlock) void bary_row_kernel(const float* acc, cons
         w[base + s] = wv;
         if (xw) xw[base + s] = ai * wv;
     }
-    if (lane == 0) bary[row] = (float)p;
-    if (cnt) atomicAdd(nfloor, (unsigned long long)cnt);
+    if (lane == 0) {
+        bary[row] = (float)p;
+        if (nfloor && cnt) atomicAdd(nfloor, (unsigned long long)cnt);
+    }
 }
 
 // ------------------------------------------------------------------ K5

@@ -35,7 +35,7 @@ StepArgs base_args(gs_plan_s& P) {
     a.K = P.K;
     a.acc = P.ACC.p;
     a.acc2 = P.ACC2.p;
-    a.nfloor = P.nfloor.p;
+    a.nfloor = P.count_floors ? P.nfloor.p : nullptr;
     a.long_thr = P.nlong > 0 ? P.long_thr : 0;
     a.nlong = P.nlong;
     a.long_rows = P.long_rows.p;
@@ -62,9 +62,10 @@ void run_graph(gs_plan_s& P, const std::string& key, hipStream_t st, F&& body) {
         GS_HIP(hipGetLastError());
         return;
     }
-    const std::string full = P.kernel == GS_KERNEL_EULER
-                                 ? key + ":E" + std::to_string(P.euler_N) + "." + std::to_string(P.cg_m)
-                                 : key;
+    const std::string full = (P.kernel == GS_KERNEL_EULER
+                                  ? key + ":E" + std::to_string(P.euler_N) + "." + std::to_string(P.cg_m)
+                                  : key) +
+                             (P.count_floors ? ":F" : "");
     auto it = P.graphs.find(full);
     if (it == P.graphs.end()) {
         GS_HIP(hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal));
@@ -331,7 +332,8 @@ void enqueue_euler_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Sca
         rhs = P.ACC.p;
     }
     if (mode == ApplyMode::Scale)
-        launch_scale_epilogue(P.ACC.p, epi.num, epi.out, epi.out_a, epi.a, epi.rec, phi, P.nfloor.p, P.n, P.ldp, st);
+        launch_scale_epilogue(P.ACC.p, epi.num, epi.out, epi.out_a, epi.a, epi.rec, phi,
+                              P.count_floors ? P.nfloor.p : nullptr, P.n, P.ldp, st);
 }
 
 }  // namespace
@@ -440,6 +442,7 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
 // ------------------------------------------------------------------ heat apply
 void heat_apply(gs_plan_s& P, double lam, double t, const float* X, float* Y, float* Ydt, hipStream_t st) {
     const bool dual = Ydt != nullptr;
+    P.count_floors = false;
     if (dual && !P.ACC2.p) P.ACC2.alloc(P.sz());
     set_coefs(P, lam, t, st);
     launch_copy_ld(X, P.B, P.X.p, P.ldp, P.n, P.B, st);
@@ -513,6 +516,7 @@ void use_record_buffer(gs_plan_s& P, const float* rec) {
 void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J, float phi,
               int C, float* ckpt, float* v, float* w, double* dist, double* marg, int64_t* nfl, hipStream_t st) {
     const bool has_a = a != nullptr;
+    P.count_floors = nfl != nullptr;
     set_coefs(P, lam, t, st);
     load_inputs(P, a, mu, nu, st);
     launch_fill(P.w.p, 1.f, P.sz(), st);
@@ -564,6 +568,7 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
                        float phi, int C, const float* ckpt, const double* gd, float* gmu, float* gnu, double* gt,
                        hipStream_t st) {
     const bool has_a = a != nullptr;
+    P.count_floors = false;
     const size_t sz = P.sz();
     if (!P.ACC2.p) P.ACC2.alloc(sz);
     if (P.seg_cap < C) {
@@ -613,9 +618,9 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
         use_record_buffer(P, ckpt);
         const float* rec = ckpt;
         launch_scale_epilogue(rec + 2 * (size_t)(J - 1) * sz, P.mu.p, P.v.p, nullptr, nullptr, nullptr, phi,
-                              P.nfloor.p, P.n, P.ldp, st);
+                              nullptr, P.n, P.ldp, st);
         launch_scale_epilogue(rec + (2 * (size_t)(J - 1) + 1) * sz, P.nu.p, P.w.p, nullptr, nullptr, nullptr, phi,
-                              P.nfloor.p, P.n, P.ldp, st);
+                              nullptr, P.n, P.ldp, st);
         reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
         launch_bwd_seed(P.mu.p, P.nu.p, P.v.p, P.w.p, ap, P.g4t.p, P.n, P.ldp, P.dmu.p, P.dnu.p, P.vseed.p, P.wbar.p,
                         st);
@@ -671,6 +676,7 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
 void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float* mus, const double* alpha, int J,
                 float phi, float* bary, float* v, float* w, double* marg, int64_t* nfl, hipStream_t st) {
     const bool has_a = a != nullptr;
+    P.count_floors = nfl != nullptr;
     if (!P.alpha.p) P.alpha.alloc(P.ldp);
     if (!P.bary.p) P.bary.alloc(P.n);
     set_coefs(P, lam, t, st);
@@ -689,7 +695,7 @@ void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float*
             enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Scale, e1, phi, s);
             enqueue_apply(P, has_a ? P.xv.p : P.v.p, ApplyMode::Store, ScaleEpi{}, phi, s);
             launch_bary_row(P.ACC.p, P.alpha.p, P.n, P.ldp, P.B, phi, P.bary.p, P.w.p, has_a ? P.xw.p : nullptr, ap,
-                            P.nfloor.p, s);
+                            P.count_floors ? P.nfloor.p : nullptr, s);
         });
     }
     GS_HIP(hipMemcpyAsync(bary, P.bary.p, P.n * sizeof(float), hipMemcpyDeviceToDevice, st));

@@ -85,3 +85,29 @@ def test_pairs_beyond_K_hops_match_the_floor_closed_form(gs):
     assert np.all(np.abs(out["dist"] - ref) <= 1e-5 * np.maximum(np.abs(ref), 4 * t)), (out["dist"], ref)
     smu, snu = int((mu > 0).sum()), int((nu > 0).sum())
     assert out["n_floored"] == snu + (J - 1) * (smu + snu)
+
+
+def test_floor_count_is_optional_and_changes_nothing(gs):
+    """Without n_floored the kernels skip the count; results stay bitwise equal."""
+    n, K, t, J, phi = 400, 20, 1.5, 6, 1e-30
+    g = gs.gs_graph_from_csr(n, *synth.cycle_graph(n))
+    rng = np.random.default_rng(4)
+    mu = np.zeros((n, 2), dtype=np.float32)
+    nu = np.zeros((n, 2), dtype=np.float32)
+    mu[[0, 1, 2, 3], 0] = rng.dirichlet(np.ones(4))
+    nu[[150, 151, 153], 0] = rng.dirichlet(np.ones(3))
+    mu[[300, 302], 1] = rng.dirichlet(np.ones(2))
+    nu[[100, 101, 102, 103, 104], 1] = rng.dirichlet(np.ones(5))
+    plan = gs.Plan(g, K, 2)
+    with_count = gs.gs_sinkhorn(plan, 4.0, t, to_dev(mu), to_dev(nu), J, phi=phi, want_floors=True)
+    without = gs.gs_sinkhorn(plan, 4.0, t, to_dev(mu), to_dev(nu), J, phi=phi)
+    assert without["n_floored"] is None
+    assert np.array_equal(with_count["dist"], without["dist"])
+    smu, snu = int((mu > 0).sum()), int((nu > 0).sum())
+    assert with_count["n_floored"] == snu + (J - 1) * (smu + snu)
+    bplan = gs.Plan(g, K, 2)
+    b1 = torch.empty(n, device="cuda")
+    b2 = torch.empty(n, device="cuda")
+    gs.gs_barycenter(bplan, 4.0, t, to_dev(mu), np.array([0.5, 0.5]), 5, b1, want_floors=True)
+    gs.gs_barycenter(bplan, 4.0, t, to_dev(mu), np.array([0.5, 0.5]), 5, b2)
+    assert torch.equal(b1, b2)
