@@ -108,6 +108,33 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
+def test_gradient_matches_fp64_finite_differences(gs, clusters):
+    """The GPU gradient (record mode) against central differences of the float64
+    oracle's forward: 16 random support coordinates of mu with relative step
+    1e-4, and t with step 1e-4 (one pair, K = 30, t = 2, J = 20)."""
+    n, labels, arrs, L = clusters
+    K, t, J = 30, 2.0, 20
+    rng = np.random.default_rng(123)
+    mu, nu = _grad_case(n, labels, 1, rng)
+    lam = lam_hat_of(L)
+    m64, n64 = mu[:, 0].astype(np.float64), nu[:, 0].astype(np.float64)
+    coords = rng.choice(np.nonzero(m64 > 0)[0], size=16, replace=False)
+    fd = osk.finite_diff_mu(L, lam, t, K, m64, n64, J, coords)
+    fdt = osk.finite_diff_t(L, lam, t, K, m64, n64, J)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, 1)
+    mud, nud = to_dev(mu), to_dev(nu)
+    rec = torch.empty(gs.ckpt_floats(plan, J, gs.GS_RECORD_ALL), device="cuda")
+    gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=gs.GS_RECORD_ALL, ckpt=rec)
+    gmu = torch.empty(n, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, gs.GS_RECORD_ALL, rec, [1.0], grad_mu=gmu)
+    got = to_host(gmu)[coords]
+    full = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J)["dmu"][:, 0]
+    scale = np.maximum(np.abs(fd), 1e-2 * np.abs(full[m64 > 0]).max())
+    assert np.all(np.abs(got - fd) <= 1e-4 * scale), np.abs(got - fd) / scale
+    assert gt[0] == pytest.approx(fdt[0], rel=1e-4)
+
+
 @pytest.mark.parametrize("ce", [5, -1])
 def test_autograd_function(gs, clusters, ce):
     """Through torch.autograd, with checkpoints every 5 iterations and with records (-1)."""
