@@ -68,3 +68,20 @@ def test_record_mode_equals_checkpointed_sweep(gs, swiss, B, weighted):
         for i in (1, 2, 3, 4):
             assert torch.equal(rec[i], ref[i]), (again, i)
         np.testing.assert_allclose(rec[5], ref[5], rtol=1e-6, atol=1e-6 * np.abs(ref[5]).max())
+
+
+def test_record_mode_single_iteration(gs, swiss):
+    """J = 1: one record chunk of one iteration; the sweep's only reduction uses w^0 = 1."""
+    arrs, L = swiss
+    n, K, t, J, B = 2000, 20, 1.0, 1, 3
+    g = gs.gs_graph_from_csr(n, *arrs)
+    rng = np.random.default_rng(77)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1)
+    plan = gs.Plan(g, K, B)
+    ref = _run(gs, plan, lam_hat_of(L), t, to_dev(mu), to_dev(nu), J, 1, None)
+    rec = _run(gs, plan, lam_hat_of(L), t, to_dev(mu), to_dev(nu), J, gs.GS_RECORD_ALL, None)
+    assert np.array_equal(rec[0]["dist"], ref[0]["dist"])
+    for i in (1, 2, 3, 4):
+        assert torch.equal(rec[i], ref[i]), i
+    np.testing.assert_allclose(rec[5], ref[5], rtol=1e-6, atol=1e-6 * np.abs(ref[5]).max())
