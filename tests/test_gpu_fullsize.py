@@ -10,7 +10,10 @@ hold at any size:
     (L 1 = 0) and symmetry <z, p_K x> = <p_K z, x>, both to float32 rounding;
   * Algorithm 1 + reverse sweep: the column marginal a w p_K(a v) equals a nu
     exactly after a w-update, and the gradient agrees with central differences
-    of the GPU forward along a random direction of the supports.
+    of the GPU forward along a random direction of the supports;
+  * Algorithm 1 in the benchmark's tuned 32-column launch for 5 iterations:
+    two sampled columns against the float64 oracle run on the library's
+    exported graph with the same lambda_hat.
 """
 import os
 
@@ -128,3 +131,24 @@ def test_sinkhorn_gradient_matches_directional_differences(big):
     ftd = (gs.gs_sinkhorn(plan, lam, t + ht, mud, nud, J)["dist"]
            - gs.gs_sinkhorn(plan, lam, t - ht, mud, nud, J)["dist"]) / (2 * ht)
     np.testing.assert_allclose(gt, ftd, rtol=2e-3, atol=1e-3 * np.abs(gt).max())
+
+
+def test_sinkhorn_columns_match_oracle_at_full_size(big):
+    """The benchmark's launch configuration (tuned 32-column plan, K = 50, t = 2)
+    for J = 5 iterations, two sampled columns against the float64 oracle run on
+    the library's exported graph (float32 weights) with the same lambda_hat."""
+    gs, X, g, lam = big
+    n, K, t, J, B = g.n, 50, 2.0, 5, 32
+    sizes = synth.loguniform_support_sizes(n, 2 * B, 5000, 200000, 91)
+    H = np.stack([synth.histogram_on_random_support(n, int(s), 1.0, 910 + i) for i, s in enumerate(sizes)], axis=1)
+    mu, nu = H[:, :B].copy(), H[:, B:].copy()
+    plan = gs.Plan(g, K, B, flags=gs.GS_PLAN_AUTOTUNE, tune_cache=TUNE)
+    out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J)
+    rp, col, w, _ = g.export()
+    L = ograph.laplacian(ograph.csr_from_arrays(n, rp, col, w.astype(np.float64)))
+    cols = [0, 17]
+    from oracle import sinkhorn as osk
+    ref = osk.sinkhorn(L, lam, t, K, mu[:, cols].astype(np.float64), nu[:, cols].astype(np.float64), J,
+                       marginals=False)["D"]
+    got = out["dist"][cols]
+    assert np.all(np.abs(got - ref) <= 1e-5 * np.maximum(np.abs(ref), 4 * t)), (got, ref)
