@@ -108,6 +108,35 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
+@pytest.mark.parametrize("ce", [7, -1])
+def test_backward_with_vertex_weights_matches_oracle(gs, clusters, ce):
+    """Vertex weights a (R7) through forward and reverse sweep, checkpointed and recorded."""
+    n, labels, arrs, L = clusters
+    B, K, t, J = 3, 30, 1.5, 15
+    rng = np.random.default_rng(55)
+    mu, nu = _grad_case(n, labels, B, rng)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    lam = lam_hat_of(L)
+    gd = np.array([1.0, -0.7, 0.4])
+    ref = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J,
+                            a=a.astype(np.float64), g=gd)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    mud, nud, ad = to_dev(mu), to_dev(nu), to_dev(a)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, a=ad, ckpt_every=ce, ckpt=ckpt)
+    assert (np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)).all()
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, gd, a=ad, grad_mu=gmu, grad_nu=gnu)
+    for got, want, h in ((to_host(gmu).reshape(n, B), ref["dmu"], mu), (to_host(gnu).reshape(n, B), ref["dnu"], nu)):
+        for b in range(B):
+            s_ = h[:, b] > 0
+            rel = np.linalg.norm(got[s_, b] - want[s_, b]) / np.linalg.norm(want[s_, b])
+            assert rel <= 1e-4, (b, rel)
+    np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
+
+
 def test_gradient_matches_fp64_finite_differences(gs, clusters):
     """The GPU gradient (record mode) against central differences of the float64
     oracle's forward: 16 random support coordinates of mu with relative step
