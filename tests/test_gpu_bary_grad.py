@@ -53,6 +53,23 @@ def test_barycenter_matches_oracle(gs, clusters):
     np.testing.assert_allclose(out["marg_err"], ref["marg_row"], rtol=0.05, atol=2e-7)
 
 
+def test_barycenter_with_vertex_weights_matches_oracle(gs, clusters):
+    """Vertex weights a (R7) in the barycenter iteration: m = 5 inputs, K = 30, t = 1."""
+    n, labels, arrs, L = clusters
+    m, K, t, J = 5, 30, 1.0, 30
+    rng = np.random.default_rng(71)
+    H, _ = synth.loguniform_support_histograms(n, m, 30, 1500, 0.5, rng)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    alpha = np.array([0.1, 0.2, 0.3, 0.25, 0.15])
+    lam = lam_hat_of(L)
+    ref = osk.barycenter(L, lam, t, K, H.astype(np.float64), alpha, J, a=a.astype(np.float64))
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, m)
+    bary = torch.empty(n, device="cuda")
+    gs.gs_barycenter(plan, lam, t, to_dev(H), alpha, J, bary, a=to_dev(a))
+    assert np.abs(to_host(bary) - ref["p"]).sum() <= 1e-6, np.abs(to_host(bary) - ref["p"]).sum()
+
+
 def test_barycenter_single_input_is_smoothed_input(gs, clusters):
     n, labels, arrs, L = clusters
     K, t = 30, 1.0
