@@ -8,7 +8,9 @@ sizes log-uniform in [5k, 200k] (Dirichlet(1) weights on random nodes); the
 32,896 pairs i <= j of the 256 x 256 distance matrix are processed in batches
 of P pairs.  One step = Algorithm 1 for one batch of P pairs (J = 200
 iterations) plus the hand-written reverse sweep giving d D / d mu, d D / d nu
-and d D / d t for every pair.  By default the forward records every
+and d D / d t for every pair, whose histogram gradients are then added into
+the gradient of the total distance with respect to each of the 256
+histograms (256 x n, kept in HBM across steps).  By default the forward records every
 iteration's denominators in HBM (51 GB at this size) and the reverse sweep
 recomputes nothing; --ckpt-every C > 0 checkpoints w every C iterations
 instead and recomputes each segment.
@@ -347,7 +349,9 @@ def main():
     for b in batches:
         mu = torch.stack([Hd[int(i)] for i in b[:, 0]], dim=1).contiguous()
         nu = torch.stack([Hd[int(j)] for j in b[:, 1]], dim=1).contiguous()
-        dev_batches.append((mu, nu))
+        ci = torch.from_numpy(b[:, 0].astype(np.int32)).to(dev)
+        cj = torch.from_numpy(b[:, 1].astype(np.int32)).to(dev)
+        dev_batches.append((mu, nu, ci, cj))
     del Hd
     log(f"[setup] {len(need)} histograms, {nbatch} batches of {P} pairs in {time.perf_counter() - t0:.1f}s")
 
@@ -388,9 +392,16 @@ def main():
     gnu = torch.empty(n * P, device=dev)
     ones = np.ones(P)
 
-    def step(mu, nu):
+    # gradient of the total distance with respect to every one of the m histograms
+    # (m x n, distribution-major), summed over the batches' pairs
+    G = torch.zeros((m, n), dtype=torch.float32, device=dev)
+    log(f"[setup] per-histogram gradients: {G.numel() * 4 / 1e9:.1f} GB")
+
+    def step(mu, nu, ci, cj):
         out = gs.gs_sinkhorn(plan, lam, t, mu, nu, J, ckpt_every=ce, ckpt=ckpt)
         gt = gs.gs_sinkhorn_backward(plan, lam, t, mu, nu, J, ce, ckpt, ones, grad_mu=gmu, grad_nu=gnu)
+        gs.gs_accumulate_columns(gmu.view(n, P), ci, G)
+        gs.gs_accumulate_columns(gnu.view(n, P), cj, G)
         return out["dist"], gt
 
     for w in range(args.warmup):
@@ -417,7 +428,7 @@ def main():
     ms_per_step = max(ms_total, wall * 1e3) / args.steps
     applies_per_step = P * (2 * J + 2 * J)
     value = applies_per_step / (ms_per_step / 1e3)
-    finite = all(np.all(np.isfinite(d)) for d in dists)
+    finite = all(np.all(np.isfinite(d)) for d in dists) and bool(torch.isfinite(G).all())
 
     # ---------------------------------------------------------------- fused step roofline (HIP events)
     step_ms, step_bytes = gs.gs_plan_time_step(plan, reps=10)
@@ -519,7 +530,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": ("50 Gaussian clusters x %d on a 2-D spline surface in R^100, sigma 0.1; "
                                 "symmetrised k=%d kNN; K=%d, t=%g; J=%d Sinkhorn iterations; "
-                                "%d pairs per step from the 256x256 pair matrix; forward + reverse sweep (%s)"
+                                "%d pairs per step from the 256x256 pair matrix; forward + reverse sweep (%s); "
+                                "pair gradients summed into the total's gradient for each of the 256 histograms"
                                 % (args.per_cluster, args.knn, K, t, J, P,
                                    "from recorded denominators" if ce == gs.GS_RECORD_ALL
                                    else f"checkpoints every {ce}, segments recomputed")),

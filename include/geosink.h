@@ -277,6 +277,26 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
 gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, hipStream_t stream,
                          double* out);
 
+/* Per-distribution gradients from a batch's per-pair gradients.  When the B
+ * pairs of a gs_sinkhorn batch draw their columns from m distributions (all
+ * pairs of the Sec. "Nearest-Wasserstein-neighbor distributions" experiment),
+ * the gradient of the sum of their distances with respect to distribution c
+ * is, by the chain rule, the sum of the gradient columns drawn from c; call
+ * once with grad_mu and the pairs' source indices and once with grad_nu and
+ * their target indices (a pair (c, c) then collects both columns).
+ *   src   device n x B float32, node-major (grad_mu or grad_nu of
+ *         gs_sinkhorn_backward).
+ *   cols  device B int32: the distribution of each column; entries outside
+ *         [0, m) are skipped (e.g. -1 for a batch's padding columns).
+ *   G     device m x n float32, distribution-major (distribution c's
+ *         gradient is the n-vector at G + c*n), read and updated:
+ *         G[c*n + i] += src[i*B + b] for every b with cols[b] = c, in the
+ *         order b = 0, 1, ..., B-1 (one thread per node i: deterministic,
+ *         also when cols repeats an index).  G must not overlap src.
+ *   1 <= n < 2^31, 1 <= B <= 4096, m >= 1.  Asynchronous; allocates nothing. */
+gs_status gs_accumulate_columns(const float* src, int64_t n, int32_t B, const int32_t* cols, int32_t m,
+                                float* G, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Measurement helpers                                                        */
 /* ------------------------------------------------------------------------ */

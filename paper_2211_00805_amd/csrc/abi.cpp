@@ -335,6 +335,19 @@ gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_
     });
 }
 
+gs_status gs_accumulate_columns(const float* src, int64_t n, int32_t B, const int32_t* cols, int32_t m, float* G,
+                                hipStream_t stream) {
+    return guarded([&] {
+        GS_REQUIRE(src != nullptr && cols != nullptr && G != nullptr, "src / cols / G is NULL");
+        GS_REQUIRE(n >= 1 && n < (int64_t)1 << 31, "n must be in [1, 2^31)");
+        GS_REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+        GS_REQUIRE(m >= 1, "m must be >= 1");
+        GS_REQUIRE((const float*)G != src, "src and G must not overlap");
+        launch_accumulate_columns(src, n, B, cols, m, G, stream);
+        GS_HIP(hipGetLastError());
+    });
+}
+
 gs_status gs_stream_gather(const float* X, int64_t n, const int32_t* idx, int64_t m, float* out,
                            hipStream_t stream) {
     return guarded([&] {

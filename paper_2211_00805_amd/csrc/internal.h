@@ -196,6 +196,10 @@ void launch_scale_epilogue(const float* acc, const float* num, float* out, float
 int64_t gather_out_floats(int64_t m);
 void launch_gather_rows(const float* X, int64_t n, const int32_t* idx, int64_t m, float* out, hipStream_t st);
 
+// G[cols[b]*n + i] += src[i*B + b] for cols[b] in [0, m), b = 0..B-1 in order (accumulate.hip)
+void launch_accumulate_columns(const float* src, int64_t n, int B, const int32_t* cols, int m, float* G,
+                               hipStream_t st);
+
 // kNN candidates (knn.hip): cand (n x kk) int32, candidate ids sorted by fp32 Gram distance
 void launch_knn_candidates(const float* Xc, const float* norms, int64_t n, int d, int kk, int32_t* cand,
                            hipStream_t st);

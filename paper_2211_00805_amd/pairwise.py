@@ -12,7 +12,11 @@ B = `batch` (or the next power of two above P when there are only P < batch
 pairs); a short last batch is padded with copies of its first pair, whose
 results are dropped.  Widths whose padded row (B rounded up to 4 floats) is a
 power of two let each gathered row be read by one group of lanes in one
-pass: at n = 150k an odd width such as 35 costs 5x more per launch than 32.  The scores are plain definitions over the m x m
+pass: at n = 150k an odd width such as 35 costs 5x more per launch than 32.
+With `grad`, each batch also runs the reverse sweep (`gs_sinkhorn_backward`,
+reading the forward's recorded denominators) and `gs_accumulate_columns` adds
+its per-pair gradients into the per-histogram gradients of the total of the
+computed distances.  The scores are plain definitions over the m x m
 matrices.
 """
 from __future__ import annotations
@@ -20,7 +24,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .api import Graph, Plan, gs_sinkhorn
+from .api import (GS_RECORD_ALL, Graph, Plan, ckpt_floats, gs_accumulate_columns, gs_sinkhorn,
+                  gs_sinkhorn_backward)
 
 
 def pair_list(m: int, diagonal: bool = False) -> np.ndarray:
@@ -30,25 +35,35 @@ def pair_list(m: int, diagonal: bool = False) -> np.ndarray:
 
 def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.Tensor, iters: int,
                     batch: int = 32, diagonal: bool = False, phi: float = 1e-30, plan: Plan | None = None,
-                    plan_flags: int = 0, tune_cache: str | None = None) -> np.ndarray:
+                    plan_flags: int = 0, tune_cache: str | None = None, grad: bool = False):
     """Symmetric m x m matrix of Algorithm 1's distances between the columns of H (n, m).
 
     D[i, j] = D[j, i] is the distance with mu = H[:, i], nu = H[:, j] (i < j);
     the diagonal holds the self-distances when `diagonal`, else 0.
+    With `grad`, returns (D, G): G (m, n) float32 on H's device holds the
+    gradient of the total sum_{computed pairs} D_ij with respect to each
+    column of H (zero off each column's support), through exactly `iters`
+    iterations; the forward records every iteration's denominators
+    (2 * iters * n * B floats of device memory).
     """
     if H.dim() != 2 or H.shape[0] != graph.n:
         raise ValueError(f"H must be (n={graph.n}, m), got {tuple(H.shape)}")
     m = H.shape[1]
     pairs = pair_list(m, diagonal)
     D = np.zeros((m, m), dtype=np.float64)
+    G = torch.zeros((m, graph.n), dtype=torch.float32, device=H.device) if grad else None
     if len(pairs) == 0:
-        return D
+        return (D, G) if grad else D
     B = min(batch, 1 << (len(pairs) - 1).bit_length())
     if plan is None:
         plan = Plan(graph, K, B, flags=plan_flags, tune_cache=tune_cache)
     elif plan.B != B or plan.K != K:
         raise ValueError("plan does not match (K, batch)")
     Ht = H.t().contiguous()                      # m x n rows: one histogram per row
+    if grad:
+        rec = torch.empty(ckpt_floats(plan, iters, GS_RECORD_ALL), dtype=torch.float32, device=H.device)
+        gmu = torch.empty((graph.n, B), dtype=torch.float32, device=H.device)
+        gnu = torch.empty_like(gmu)
     for s in range(0, len(pairs), B):
         blk = pairs[s:s + B]
         nreal = len(blk)
@@ -58,10 +73,22 @@ def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.
         jj = torch.from_numpy(blk[:, 1]).to(H.device)
         mu = Ht.index_select(0, ii).t().contiguous()
         nu = Ht.index_select(0, jj).t().contiguous()
-        d = gs_sinkhorn(plan, lambda_hat, t, mu, nu, iters, phi=phi)["dist"][:nreal]
+        if grad:
+            d = gs_sinkhorn(plan, lambda_hat, t, mu, nu, iters, phi=phi, ckpt_every=GS_RECORD_ALL,
+                            ckpt=rec)["dist"][:nreal]
+            weight = np.zeros(B)
+            weight[:nreal] = 1.0                 # padding pairs add nothing
+            gs_sinkhorn_backward(plan, lambda_hat, t, mu, nu, iters, GS_RECORD_ALL, rec, weight, phi=phi,
+                                 grad_mu=gmu, grad_nu=gnu, want_grad_t=False)
+            for side, g in ((0, gmu), (1, gnu)):
+                cols = np.full(B, -1, dtype=np.int32)
+                cols[:nreal] = blk[:nreal, side]
+                gs_accumulate_columns(g, torch.from_numpy(cols).to(H.device), G)
+        else:
+            d = gs_sinkhorn(plan, lambda_hat, t, mu, nu, iters, phi=phi)["dist"][:nreal]
         D[blk[:nreal, 0], blk[:nreal, 1]] = d
         D[blk[:nreal, 1], blk[:nreal, 0]] = d
-    return D
+    return (D, G) if grad else D
 
 
 def _average_ranks(x: np.ndarray) -> np.ndarray:

@@ -111,3 +111,79 @@ def test_floor_count_is_optional_and_changes_nothing(gs):
     gs.gs_barycenter(bplan, 4.0, t, to_dev(mu), np.array([0.5, 0.5]), 5, b1, want_floors=True)
     gs.gs_barycenter(bplan, 4.0, t, to_dev(mu), np.array([0.5, 0.5]), 5, b2)
     assert torch.equal(b1, b2)
+
+
+def _accumulate_reference(src, cols, G0):
+    """float32, one column at a time in order b = 0, 1, ...: the summation order the kernel documents."""
+    G = G0.copy()
+    for b in range(src.shape[1]):
+        c = int(cols[b])
+        if 0 <= c < G.shape[0]:
+            G[c] = (G[c] + src[:, b]).astype(np.float32)
+    return G
+
+
+@pytest.mark.parametrize("n,B,m", [(1000, 37, 7), (256, 32, 3), (1, 1, 1), (513, 64, 5)])
+def test_accumulate_columns_bit_exact(gs, n, B, m):
+    """Repeated and skipped indices (-1, m), a ragged last block of nodes and a
+    column tail past the 32-column staging: bitwise equal to the float32 loop."""
+    rng = np.random.default_rng(n + B + m)
+    src = rng.standard_normal((n, B)).astype(np.float32)
+    cols = rng.integers(-1, m + 1, B).astype(np.int32)
+    cols[0] = 0
+    if B > 2:
+        cols[1] = cols[2] = m - 1            # a repeated index
+    G0 = rng.standard_normal((m, n)).astype(np.float32)
+    ref = _accumulate_reference(src, cols, G0)
+    G = to_dev(G0)
+    gs.gs_accumulate_columns(to_dev(src), torch.from_numpy(cols).cuda(), G)
+    out = G.cpu().numpy()
+    assert np.array_equal(out, ref), np.abs(out - ref).max()
+    # a second call adds again on top (G is read, not overwritten)
+    gs.gs_accumulate_columns(to_dev(src), torch.from_numpy(cols).cuda(), G)
+    assert np.array_equal(G.cpu().numpy(), _accumulate_reference(src, cols, ref))
+
+
+def test_accumulate_columns_rejects_bad_arguments(gs):
+    src = torch.zeros((8, 4), device="cuda")
+    G = torch.zeros((2, 8), device="cuda")
+    with pytest.raises(TypeError):
+        gs.gs_accumulate_columns(src, torch.zeros(4, dtype=torch.int64, device="cuda"), G)
+    with pytest.raises(ValueError):
+        gs.gs_accumulate_columns(src, torch.zeros(4, dtype=torch.int32, device="cuda"), torch.zeros((2, 9), device="cuda"))
+
+
+def test_distance_matrix_gradient_matches_oracle(gs):
+    """Matrix and per-histogram gradients of the total over the pairs i <= j
+    (21 pairs in batches of 8: a padded last batch) against the oracle's
+    reverse mode: distances to 1e-5 max(|D|, 4t), each histogram's gradient
+    to 1e-4 relative in norm on its support and per sampled coordinate
+    relative to max(|g|, 1e-3 max|g|).  Histograms: Dirichlet(1) weights on
+    150 random nodes each of the 480-node graph."""
+    m, per, K, t, J = 6, 80, 20, 1.0, 40
+    X, lab, means = synth.gaussians_on_swiss_roll(m, per, sigma=4.0, workload=7)
+    arrs, L, info, A = oracle_csr(X, 10)
+    assert info["n_components"] == 1
+    n = X.shape[0]
+    lam = lam_hat_of(L)
+    rng = np.random.default_rng(9)
+    H = np.zeros((n, m), dtype=np.float32)
+    for i in range(m):                           # random supports (no floored denominator)
+        idx = rng.choice(n, 150, replace=False)
+        H[idx, i] = rng.dirichlet(np.ones(150))
+    H64 = H.astype(np.float64)
+    total_ref, G_ref = opw.total_gradient(L, lam, t, K, H64, J, diagonal=True)
+    D_ref = opw.distance_matrix(L, lam, t, K, H64, J, diagonal=True)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    D, G = gs.distance_matrix(g, lam, t, K, to_dev(H), J, batch=8, diagonal=True, grad=True)
+    assert np.all(np.abs(D - D_ref) <= 1e-5 * np.maximum(np.abs(D_ref), 4 * t)), np.abs(D - D_ref).max()
+    assert abs(np.sum(np.triu(D)) - total_ref) <= 1e-5 * max(abs(total_ref), 4 * t * len(D_ref))
+    Gh = G.cpu().numpy().astype(np.float64).T        # (n, m) like the oracle
+    assert np.all(Gh[H == 0] == 0)
+    for c in range(m):
+        sup = H[:, c] > 0
+        gr, gg = G_ref[sup, c], Gh[sup, c]
+        assert np.linalg.norm(gg - gr) <= 1e-4 * np.linalg.norm(gr), (c, np.linalg.norm(gg - gr) / np.linalg.norm(gr))
+        pick = rng.choice(len(gr), 16, replace=False)
+        scale = np.maximum(np.abs(gr[pick]), 1e-3 * np.abs(gr).max())
+        assert np.all(np.abs(gg[pick] - gr[pick]) <= 1e-4 * scale), c

@@ -84,3 +84,32 @@ def test_pairs_beyond_K_hops_reduce_to_the_floor_closed_form():
     np.testing.assert_allclose(out["D"], 4 * t * (xlx(mu) + xlx(nu)), rtol=1e-13)
     smu, snu = (mu > 0).sum(), (nu > 0).sum()
     assert out["n_floored"] == snu + (J - 1) * (smu + snu)
+
+
+def test_total_gradient_matches_finite_differences_of_the_total():
+    """G[r, c] against central differences of the total (relative step 1e-4 on H[r, c]),
+    with and without the diagonal pairs: a dropped target-side term or a
+    diagonal pair counted once fails it."""
+    X = np.random.default_rng(2).standard_normal((30, 3))
+    A, info = graph.knn_graph(X, 5)
+    L = graph.laplacian(A)
+    lam = 1.01 * spectrum.lambda_max(L)
+    rng = np.random.default_rng(3)
+    H = rng.uniform(0.2, 1, (30, 4)) * (rng.uniform(0, 1, (30, 4)) < 0.6)
+    H /= H.sum(axis=0)
+    t, K, J = 1.0, 20, 30
+    coords = [(r, c) for c in range(4) for r in np.flatnonzero(H[:, c] > 0)[:2]]
+    for diagonal in (False, True):
+        total, G = pairwise.total_gradient(L, lam, t, K, H, J, diagonal=diagonal)
+        D = pairwise.distance_matrix(L, lam, t, K, H, J, diagonal=diagonal)
+        assert abs(total - np.sum(np.triu(D))) <= 1e-12 * abs(total)
+        assert np.all(G[H == 0] == 0)
+        for r, c in coords:
+            h = 1e-4 * H[r, c]
+            Hp, Hm = H.copy(), H.copy()
+            Hp[r, c] += h
+            Hm[r, c] -= h
+            tp = pairwise.total_gradient(L, lam, t, K, Hp, J, diagonal=diagonal)[0]
+            tm = pairwise.total_gradient(L, lam, t, K, Hm, J, diagonal=diagonal)[0]
+            fd = (tp - tm) / (2 * h)
+            assert abs(G[r, c] - fd) <= 1e-6 * max(abs(fd), 1.0), (diagonal, r, c, G[r, c], fd)
