@@ -152,3 +152,30 @@ def test_sinkhorn_columns_match_oracle_at_full_size(big):
                        marginals=False)["D"]
     got = out["dist"][cols]
     assert np.all(np.abs(got - ref) <= 1e-5 * np.maximum(np.abs(ref), 4 * t)), (got, ref)
+
+
+def test_gradient_accumulation_at_full_size():
+    """The benchmark's per-histogram accumulation at its size (n = 1M, 32
+    columns into 256 x n, two calls): sampled nodes and both ends, bitwise
+    equal to the float32 sums in column order; rows of G that no column
+    names stay zero."""
+    need_gpu()
+    import paper_2211_00805_amd as gs
+    n, B, m = 1_000_000, 32, 256
+    rng = np.random.default_rng(23)
+    src = rng.standard_normal((n, B)).astype(np.float32)
+    cols = rng.integers(0, m, B).astype(np.int32)
+    cols[5] = cols[6] = cols[7]                       # a histogram in three pairs of the batch
+    G = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    dcols = torch.from_numpy(cols).cuda()
+    gs.gs_accumulate_columns(to_dev(src), dcols, G)
+    gs.gs_accumulate_columns(to_dev(src[:, ::-1].copy()), dcols, G)
+    nodes = np.concatenate([[0, 1, 255, 256, n - 1], rng.choice(n, 4000, replace=False)])
+    ref = np.zeros((m, len(nodes)), dtype=np.float32)
+    for s in (src, src[:, ::-1]):
+        for b in range(B):
+            ref[cols[b]] = (ref[cols[b]] + s[nodes, b]).astype(np.float32)
+    got = G[:, torch.from_numpy(nodes).cuda()].cpu().numpy()
+    assert np.array_equal(got, ref)
+    untouched = np.setdiff1d(np.arange(m), cols)
+    assert float(G[torch.from_numpy(untouched).cuda()].abs().max()) == 0.0
