@@ -15,7 +15,10 @@
  *    aborts, throws or prints.  gs_last_error() returns a thread-local message
  *    describing the last failure on the calling thread.
  *  - Argument validation happens before any HIP call; a call that fails
- *    validation has no effect.
+ *    validation has no effect.  The contents of device arrays that must be
+ *    finite and >= 0 (histograms, vertex weights) can only be checked on the
+ *    device: they are counted while the call runs and reported when it
+ *    synchronises (gs_sinkhorn, gs_sinkhorn_backward, gs_barycenter).
  *  - Ownership: gs_graph and gs_plan handles are created and freed by the
  *    library.  Every array argument is owned by the caller and only borrowed
  *    for the duration of the call (device work reading or writing it is
@@ -204,8 +207,13 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
 #define GS_RECORD_ALL (-1)
 
 /* Algorithm 1 (Geodesic Sinkhorn) for B independent pairs (column b of mu, nu).
- *   a        device n vertex weights, or NULL for all ones.
- *   mu, nu   device n x B, finite, >= 0 (not renormalised).
+ *   a        device n vertex weights (finite, >= 0), or NULL for all ones.
+ *   mu, nu   device n x B, finite, >= 0 (not renormalised).  Being device
+ *            data, these are checked on the device while the call runs: when
+ *            the call synchronises (any host output requested) it fails with
+ *            GS_ERR_NONFINITE for a non-finite entry of mu, nu or a, else
+ *            GS_ERR_INVALID for a negative one (outputs then unspecified); a
+ *            call with no host output does not report them.
  *   iters    J >= 1 Sinkhorn iterations, w^0 = 1, v updated before w.
  *   phi      denominator floor (> 0, e.g. 1e-30): d = r if r > phi else phi.
  *   ckpt_every, ckpt   if ckpt != NULL, w^{s*C} (C = ckpt_every >= 1) is
@@ -245,7 +253,9 @@ gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, co
  *              the support of mu (resp. nu) are set to 0 (the derivative is
  *              -infinity there).
  *   grad_t     host B doubles or NULL (per-pair dD_b/dt times grad_dist[b]).
- * Synchronises `stream` when grad_t is requested. */
+ * mu, nu and a are checked on the device as in gs_sinkhorn and reported
+ * (GS_ERR_NONFINITE, GS_ERR_INVALID) at the end of every call.
+ * Synchronises `stream`. */
 gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const float* a,
                                const float* mu, const float* nu, int32_t iters, float phi,
                                int32_t ckpt_every, const float* ckpt, const double* grad_dist,
@@ -255,7 +265,9 @@ gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const flo
  * with discrete support"; the paper gives no algorithm: iterative Bregman
  * projections, v_i = mu_i / p_K(a w_i), q_i = floor(p_K(a v_i)),
  * p = exp(sum_i alpha_i ln q_i), w_i = p / q_i, from w_i = 1).
- *   mus      device n x m inputs; alpha host m doubles (>= 0).
+ *   mus      device n x m inputs (finite, >= 0; checked on the device and
+ *            reported as in gs_sinkhorn, with a, when marg_err or n_floored
+ *            is requested); alpha host m doubles (>= 0).
  *   bary     device n output p.  v, w: device n x m outputs or NULL.
  *   marg_err host m doubles or NULL: ||a v_i p_K(a w_i) - a mu_i||_1.
  *   n_floored host int64 or NULL: floored denominators (on mu_i's support

@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <fstream>
+#include <initializer_list>
 #include <memory>
 #include <sstream>
+#include <utility>
 
 namespace gs {
 
@@ -390,6 +392,7 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
     P->partials.alloc((size_t)reduce_blocks(P->n) * P->ldp);
     P->red.alloc(P->ldp);
     P->nfloor.alloc(1);
+    P->badin.alloc(2);
     GS_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
     for (auto* b : {&P->X, &P->U, &P->V, &P->ACC, &P->mu, &P->nu, &P->v, &P->w}) launch_fill(b->p, 0.f, sz, P->cap);
     {
@@ -511,6 +514,20 @@ void use_record_buffer(gs_plan_s& P, const float* rec) {
     }
 }
 
+// Inputs that must be finite and >= 0 are counted on the device when the call
+// starts; the counts are read back where the call synchronises.
+void count_invalid_inputs(gs_plan_s& P, std::initializer_list<std::pair<const float*, size_t>> arrays,
+                          hipStream_t st) {
+    GS_HIP(hipMemsetAsync(P.badin.p, 0, 2 * sizeof(unsigned long long), st));
+    for (const auto& a : arrays)
+        if (a.first) launch_count_invalid(a.first, (int64_t)a.second, P.badin.p, st);
+}
+
+void report_invalid_inputs(const unsigned long long* bad, const char* what) {
+    if (bad[0]) fail(GS_ERR_NONFINITE, std::string(what) + " hold " + std::to_string(bad[0]) + " non-finite entries");
+    if (bad[1]) fail(GS_ERR_INVALID, std::string(what) + " hold " + std::to_string(bad[1]) + " negative entries");
+}
+
 }  // namespace
 
 void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* mu, const float* nu, int J, float phi,
@@ -518,6 +535,8 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
     const bool has_a = a != nullptr;
     P.count_floors = nfl != nullptr;
     set_coefs(P, lam, t, st);
+    const size_t nB = (size_t)P.n * P.B;
+    count_invalid_inputs(P, {{mu, nB}, {nu, nB}, {a, (size_t)P.n}}, st);
     load_inputs(P, a, mu, nu, st);
     launch_fill(P.w.p, 1.f, P.sz(), st);
     if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
@@ -554,11 +573,13 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
     }
     if (v) launch_copy_ld(P.v.p, P.ldp, v, P.B, P.n, P.B, st);
     if (w) launch_copy_ld(P.w.p, P.ldp, w, P.B, P.n, P.B, st);
-    unsigned long long nf = 0;
+    unsigned long long nf = 0, bad[2] = {0, 0};
     if (nfl) GS_HIP(hipMemcpyAsync(&nf, P.nfloor.p, sizeof(nf), hipMemcpyDeviceToHost, st));
     GS_HIP(hipGetLastError());
     if (dist || marg || nfl) {
+        GS_HIP(hipMemcpyAsync(bad, P.badin.p, sizeof(bad), hipMemcpyDeviceToHost, st));
         GS_HIP(hipStreamSynchronize(st));
+        report_invalid_inputs(bad, "mu / nu / a");
         if (nfl) *nfl = (int64_t)nf;
     }
 }
@@ -582,6 +603,7 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
         P.tbar.alloc(P.ldp);
     }
     set_coefs(P, lam, t, st);
+    count_invalid_inputs(P, {{mu, (size_t)P.n * P.B}, {nu, (size_t)P.n * P.B}, {a, (size_t)P.n}}, st);
     load_inputs(P, a, mu, nu, st);
     std::vector<float> g4(P.ldp, 0.f);
     for (int b = 0; b < P.B; ++b) g4[b] = (float)(4.0 * t * gd[b]);
@@ -666,8 +688,11 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
     if (gnu) launch_copy_ld(P.dnu.p, P.ldp, gnu, P.B, P.n, P.B, st);
     std::vector<double> tb(P.ldp, 0.0);
     if (gt) GS_HIP(hipMemcpyAsync(tb.data(), P.tbar.p, P.ldp * sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned long long bad[2] = {0, 0};
+    GS_HIP(hipMemcpyAsync(bad, P.badin.p, sizeof(bad), hipMemcpyDeviceToHost, st));
     GS_HIP(hipGetLastError());
     GS_HIP(hipStreamSynchronize(st));
+    report_invalid_inputs(bad, "mu / nu / a");
     if (gt)
         for (int b = 0; b < P.B; ++b) gt[b] = tb[b] + gd[b] * D[b] / t;
 }
@@ -680,6 +705,7 @@ void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float*
     if (!P.alpha.p) P.alpha.alloc(P.ldp);
     if (!P.bary.p) P.bary.alloc(P.n);
     set_coefs(P, lam, t, st);
+    count_invalid_inputs(P, {{mus, (size_t)P.n * P.B}, {a, (size_t)P.n}}, st);
     load_inputs(P, a, mus, nullptr, st);
     std::vector<float> al(P.ldp, 0.f);
     for (int i = 0; i < P.B; ++i) al[i] = (float)alpha[i];
@@ -707,11 +733,13 @@ void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float*
         });
         reduce_to_host(P, red_args(P, RED_MARG, P.v.p, P.ACC.p, P.mu.p, nullptr, ap), 1.0, marg, st);
     }
-    unsigned long long nf = 0;
+    unsigned long long nf = 0, bad[2] = {0, 0};
     if (nfl) GS_HIP(hipMemcpyAsync(&nf, P.nfloor.p, sizeof(nf), hipMemcpyDeviceToHost, st));
     GS_HIP(hipGetLastError());
     if (marg || nfl) {
+        GS_HIP(hipMemcpyAsync(bad, P.badin.p, sizeof(bad), hipMemcpyDeviceToHost, st));
         GS_HIP(hipStreamSynchronize(st));
+        report_invalid_inputs(bad, "mus / a");
         if (nfl) *nfl = (int64_t)nf;
     }
 }

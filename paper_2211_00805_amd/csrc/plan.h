@@ -45,6 +45,7 @@ struct gs_plan_s {
     int nlong = 0, long_thr = 0;
     gs::DevBuf<double> partials, red;
     gs::DevBuf<unsigned long long> nfloor;
+    gs::DevBuf<unsigned long long> badin;   // non-finite / negative input entries of the current call
     bool count_floors = false;  // this call reports floored denominators (kernels skip the count otherwise)
     gs::DevBuf<float> alpha;   // barycenter weights (m)
     gs::DevBuf<float> bary;    // barycenter (n)

@@ -9,7 +9,9 @@
   * the smallest graph, one edge: heat applications against the two-node
     closed form, the Dirac-to-Dirac distance against -4t ln H_12 and against
     the hand-derived golden values within the truncation bound;
-  * a wide batch, B = 1024 columns.
+  * a wide batch, B = 1024 columns;
+  * negative or non-finite histogram and vertex-weight entries: reported by
+    status at the call's synchronisation, the plan unaffected.
 """
 import json
 import os
@@ -128,3 +130,63 @@ def test_wide_batch(gs, swiss):
     cols = [0, 1, 511, 1000, 1023]
     ref = heat.heat_apply(L, lam, t, K, x[:, cols].astype(np.float64))
     assert np.abs(to_host(Y).reshape(n, B)[:, cols] - ref).max() <= heat_tol(K, np.abs(x).max())
+
+
+def test_negative_and_non_finite_inputs_are_reported(gs, swiss):
+    """Histograms and vertex weights must be finite and >= 0: a NaN or an inf
+    fails with GS_ERR_NONFINITE (-6), a negative entry with GS_ERR_INVALID (-1),
+    whenever the call synchronises; the plan keeps working afterwards, with
+    bitwise the same results as before the failures."""
+    arrs, L = swiss
+    n, B, K, t, J = 2000, 3, 20, 1.0, 3
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = lam_hat_of(L)
+    plan = gs.Plan(g, K, B)
+    rng = np.random.default_rng(7)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 100, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 100, rng) for _ in range(B)], axis=1)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    good = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(a))["dist"]
+
+    def status_of(fn):
+        with pytest.raises(gs.GeoSinkError) as e:
+            fn()
+        return e.value.status, str(e.value)
+
+    bad = mu.copy()
+    bad[5, 1] = -1e-3
+    st, msg = status_of(lambda: gs.gs_sinkhorn(plan, lam, t, to_dev(bad), to_dev(nu), J))
+    assert st == -1 and "1 negative" in msg, msg
+    bad = nu.copy()
+    bad[7, 2] = np.nan
+    bad[9, 0] = np.inf
+    st, msg = status_of(lambda: gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(bad), J))
+    assert st == -6 and "2 non-finite" in msg, msg
+    bad_a = a.copy()
+    bad_a[3] = -2.0
+    st, _ = status_of(lambda: gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(bad_a)))
+    assert st == -1
+    # asynchronous call (no host output): nothing reported
+    gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(bad), J, want_dist=False)
+    torch.cuda.synchronize()
+
+    # reverse sweep (always synchronises)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, gs.GS_RECORD_ALL), device="cuda")
+    gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, ckpt_every=gs.GS_RECORD_ALL, ckpt=ckpt)
+    neg = mu.copy()
+    neg[11, 0] = -0.5
+    st, _ = status_of(lambda: gs.gs_sinkhorn_backward(plan, lam, t, to_dev(neg), to_dev(nu), J, gs.GS_RECORD_ALL,
+                                                      ckpt, np.ones(B), grad_mu=torch.empty(n * B, device="cuda")))
+    assert st == -1
+
+    # barycenter: reported with marg_err or n_floored
+    bplan = gs.Plan(g, K, B)
+    p = torch.empty(n, device="cuda")
+    nanmus = mu.copy()
+    nanmus[0, 0] = np.nan
+    st, _ = status_of(lambda: gs.gs_barycenter(bplan, lam, t, to_dev(nanmus), np.full(B, 1 / B), 2, p,
+                                               want_marg=True))
+    assert st == -6
+
+    again = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(a))["dist"]
+    assert np.array_equal(good, again)
