@@ -252,7 +252,9 @@ gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, co
  *   grad_mu, grad_nu  device n x B outputs (either may be NULL); entries off
  *              the support of mu (resp. nu) are set to 0 (the derivative is
  *              -infinity there).
- *   grad_t     host B doubles or NULL (per-pair dD_b/dt times grad_dist[b]).
+ *   grad_t     host B doubles or NULL (per-pair dD_b/dt times grad_dist[b]);
+ *              NULL skips the second accumulator and the reductions in t
+ *              (grad_mu and grad_nu are bitwise the same either way).
  * mu, nu and a are checked on the device as in gs_sinkhorn and reported
  * (GS_ERR_NONFINITE, GS_ERR_INVALID) at the end of every call.
  * Synchronises `stream`. */

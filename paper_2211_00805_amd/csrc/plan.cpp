@@ -614,21 +614,29 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
     const int nblk = reduce_blocks(P.n);
     std::vector<double> D(P.B, 0.0);
 
+    // The derivative in t needs the second accumulator (dual steps) and two
+    // reductions per iteration; without grad_t the adjoint applications are
+    // plain ones, whose first accumulator is bitwise the dual form's.
+    const bool want_t = gt != nullptr;
+    const ApplyMode adj_mode = want_t ? ApplyMode::Dual : ApplyMode::Store;
+    const std::string ttag = want_t ? ":t" : ":nt";
+
     // One reverse iteration j from its denominators d_j, e_j (w_j = nu / e_j,
     // v_j = mu / d_j); e_prev = e_{j-1} or NULL for j = 0 (w^0 = 1), w_prev =
     // the stored w^j instead of nu / e_{j-1} when given.
     auto reverse_iteration = [&](const float* dj, const float* ej, const float* e_prev, const float* w_prev,
                                  hipStream_t q) {
         launch_bwd_e(P.wbar.p, ej, P.nu.p, P.n, P.ldp, phi, P.dnu.p, P.X.p, q);
-        enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
-        launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.mu.p, dj, nullptr, ap), P.partials.p, nblk, P.tbar.p, 1,
-                      1.0, q);
+        enqueue_apply(P, P.X.p, adj_mode, ScaleEpi{}, phi, q);
+        if (want_t)
+            launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.mu.p, dj, nullptr, ap), P.partials.p, nblk, P.tbar.p,
+                          1, 1.0, q);
         launch_bwd_d(P.ACC.p, P.vseed.p, dj, P.mu.p, ap, P.n, P.ldp, phi, P.dmu.p, P.X.p, q);
-        enqueue_apply(P, P.X.p, ApplyMode::Dual, ScaleEpi{}, phi, q);
-        if (e_prev)
+        enqueue_apply(P, P.X.p, adj_mode, ScaleEpi{}, phi, q);
+        if (want_t && e_prev)
             launch_reduce(red_args(P, RED_DOT_QUOT, P.ACC2.p, P.nu.p, e_prev, nullptr, ap), P.partials.p, nblk,
                           P.tbar.p, 1, 1.0, q);
-        else
+        else if (want_t)
             launch_reduce(red_args(P, RED_DOT, P.ACC2.p, w_prev, nullptr, nullptr, ap), P.partials.p, nblk, P.tbar.p,
                           1, 1.0, q);
         launch_bwd_w(P.ACC.p, ap, P.n, P.ldp, P.wbar.p, q);
@@ -643,10 +651,11 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
                               nullptr, P.n, P.ldp, st);
         launch_scale_epilogue(rec + (2 * (size_t)(J - 1) + 1) * sz, P.nu.p, P.w.p, nullptr, nullptr, nullptr, phi,
                               nullptr, P.n, P.ldp, st);
-        reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
+        if (want_t)
+            reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
         launch_bwd_seed(P.mu.p, P.nu.p, P.v.p, P.w.p, ap, P.g4t.p, P.n, P.ldp, P.dmu.p, P.dnu.p, P.vseed.p, P.wbar.p,
                         st);
-        const std::string tag = std::string(has_a ? ":a" : ":1") + phi_tag(phi);
+        const std::string tag = std::string(has_a ? ":a" : ":1") + phi_tag(phi) + ttag;
         for (int j0 = ((J - 1) / kRecordChunk) * kRecordChunk; j0 >= 0; j0 -= kRecordChunk) {
             const int ns = std::min(kRecordChunk, J - j0);
             run_graph(P, "adjrec:" + std::to_string(j0) + ":" + std::to_string(ns) + tag, st, [&](hipStream_t q) {
@@ -670,11 +679,12 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
                 enqueue_iteration(P, has_a, phi, P.segd.p + slot * sz, P.sege.p + slot * sz, q);
         });
         if (s == nseg - 1) {
-            reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
+            if (want_t)
+                reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, D.data(), st);
             launch_bwd_seed(P.mu.p, P.nu.p, P.v.p, P.w.p, ap, P.g4t.p, P.n, P.ldp, P.dmu.p, P.dnu.p, P.vseed.p,
                             P.wbar.p, st);
         }
-        run_graph(P, "adj:" + tag, st, [&](hipStream_t q) {
+        run_graph(P, "adj:" + tag + ttag, st, [&](hipStream_t q) {
             for (int slot = ns - 1; slot >= 0; --slot) {
                 const float* dj = P.segd.p + slot * sz;
                 const float* ej = P.sege.p + slot * sz;

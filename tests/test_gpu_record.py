@@ -85,3 +85,34 @@ def test_record_mode_single_iteration(gs, swiss):
     for i in (1, 2, 3, 4):
         assert torch.equal(rec[i], ref[i]), i
     np.testing.assert_allclose(rec[5], ref[5], rtol=1e-6, atol=1e-6 * np.abs(ref[5]).max())
+
+
+@pytest.mark.parametrize("ce", [-1, 5])
+def test_histogram_gradients_without_grad_t_are_bitwise_equal(gs, swiss, ce):
+    """grad_t = NULL runs plain adjoint applications instead of the dual form
+    and skips the t reductions; grad_mu and grad_nu are bitwise those of the
+    sweep that also forms grad_t (records and checkpoint segments), also
+    when the two kinds of call alternate on one plan (separate captured graphs)."""
+    arrs, L = swiss
+    n, K, t, J, B = 2000, 20, 1.0, 13, 6
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = lam_hat_of(L)
+    rng = np.random.default_rng(91)
+    mu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1))
+    nu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1))
+    a = to_dev(rng.uniform(0.5, 1.5, n).astype(np.float32))
+    plan = gs.Plan(g, K, B)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    gs.gs_sinkhorn(plan, lam, t, mu, nu, J, a=a, ckpt_every=ce, ckpt=ckpt)
+    gd = np.linspace(0.5, 1.5, B)
+    outs = []
+    for want_t in (True, False, True, False):
+        gmu = torch.empty(n * B, device="cuda")
+        gnu = torch.empty(n * B, device="cuda")
+        gt = gs.gs_sinkhorn_backward(plan, lam, t, mu, nu, J, ce, ckpt, gd, a=a, grad_mu=gmu, grad_nu=gnu,
+                                     want_grad_t=want_t)
+        assert (gt is not None) == want_t
+        outs.append((gmu, gnu, gt))
+    for gmu, gnu, _ in outs[1:]:
+        assert torch.equal(gmu, outs[0][0]) and torch.equal(gnu, outs[0][1])
+    assert np.array_equal(outs[0][2], outs[2][2])
