@@ -233,7 +233,13 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
  *            heat application per call).
  *   n_floored host int64 or NULL: count of floored denominators on the
  *            numerators' supports over all iterations (NULL: not counted,
- *            which saves the atomic updates when floors are frequent).
+ *            which saves the atomic updates when floors are frequent).  A
+ *            lambda_hat below the largest Laplacian eigenvalue voids the
+ *            truncation bound and, far enough below, overflows the float32
+ *            recurrence: its NaN / inf denominators are floored (r > phi
+ *            fails) and show up here, not as a non-finite distance.
+ * A non-finite dist or marg_err entry (e.g. float32 overflow of v from
+ * histogram entries near FLT_MAX) fails the call with GS_ERR_NONFINITE.
  * Synchronises `stream` when any host output is requested. */
 gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, const float* mu,
                       const float* nu, int32_t iters, float phi, int32_t ckpt_every, float* ckpt,

@@ -523,6 +523,14 @@ void count_invalid_inputs(gs_plan_s& P, std::initializer_list<std::pair<const fl
         if (a.first) launch_count_invalid(a.first, (int64_t)a.second, P.badin.p, st);
 }
 
+// Host results of a call: a non-finite entry fails the call (after the
+// input checks, which explain most of them).
+void require_finite(const double* x, int count, const char* what) {
+    for (int b = 0; b < count; ++b)
+        if (!std::isfinite(x[b]))
+            fail(GS_ERR_NONFINITE, std::string(what) + " of column " + std::to_string(b) + " is not finite");
+}
+
 void report_invalid_inputs(const unsigned long long* bad, const char* what) {
     if (bad[0]) fail(GS_ERR_NONFINITE, std::string(what) + " hold " + std::to_string(bad[0]) + " non-finite entries");
     if (bad[1]) fail(GS_ERR_INVALID, std::string(what) + " hold " + std::to_string(bad[1]) + " negative entries");
@@ -581,6 +589,8 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
         GS_HIP(hipStreamSynchronize(st));
         report_invalid_inputs(bad, "mu / nu / a");
         if (nfl) *nfl = (int64_t)nf;
+        if (dist) require_finite(dist, P.B, "distance");
+        if (marg) require_finite(marg, P.B, "marginal error");
     }
 }
 
@@ -703,8 +713,10 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
     GS_HIP(hipGetLastError());
     GS_HIP(hipStreamSynchronize(st));
     report_invalid_inputs(bad, "mu / nu / a");
-    if (gt)
+    if (gt) {
         for (int b = 0; b < P.B; ++b) gt[b] = tb[b] + gd[b] * D[b] / t;
+        require_finite(gt, P.B, "gradient in t");
+    }
 }
 
 // ------------------------------------------------------------------ barycenter
@@ -751,6 +763,7 @@ void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float*
         GS_HIP(hipStreamSynchronize(st));
         report_invalid_inputs(bad, "mus / a");
         if (nfl) *nfl = (int64_t)nf;
+        if (marg) require_finite(marg, P.B, "marginal error");
     }
 }
 

@@ -11,7 +11,9 @@
     the hand-derived golden values within the truncation bound;
   * a wide batch, B = 1024 columns;
   * negative or non-finite histogram and vertex-weight entries: reported by
-    status at the call's synchronisation, the plan unaffected.
+    status at the call's synchronisation, the plan unaffected;
+  * a distance that overflows float32: GS_ERR_NONFINITE; a lambda_hat far
+    below the spectrum: counted floors.
 """
 import json
 import os
@@ -190,3 +192,40 @@ def test_negative_and_non_finite_inputs_are_reported(gs, swiss):
 
     again = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(a))["dist"]
     assert np.array_equal(good, again)
+
+
+def test_non_finite_distance_is_reported(gs):
+    """A distance that overflows float32 fails the call with GS_ERR_NONFINITE:
+    on a 400-cycle with K = 20, a mass of 1e10 at node 0 and a target at node
+    200 (beyond K hops), the second iteration's d floors at phi and
+    v = 1e10 / 1e-30 is +inf.  The same pair with unit mass is finite."""
+    n, K, t, J = 400, 20, 1.5, 2
+    g = gs.gs_graph_from_csr(n, *synth.cycle_graph(n))
+    plan = gs.Plan(g, K, 1)
+    mu = np.zeros((n, 1), dtype=np.float32)
+    nu = np.zeros((n, 1), dtype=np.float32)
+    mu[0, 0] = 1e10
+    nu[200, 0] = 1.0
+    with pytest.raises(gs.GeoSinkError) as e:
+        gs.gs_sinkhorn(plan, 4.0, t, to_dev(mu), to_dev(nu), J)
+    assert e.value.status == -6 and "distance of column 0" in str(e.value)
+    mu[0, 0] = 1.0
+    assert np.all(np.isfinite(gs.gs_sinkhorn(plan, 4.0, t, to_dev(mu), to_dev(nu), J)["dist"]))
+
+
+def test_lambda_hat_far_below_the_spectrum_shows_as_floors(gs, swiss):
+    """lambda_hat = lambda_max / 30 with K = 50: T_K(y_max) overflows float32,
+    the NaN / inf denominators are floored and counted; with a valid
+    lambda_hat the same call floors nothing."""
+    arrs, L = swiss
+    n, K, t, J, B = 2000, 50, 2.0, 2, 2
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = lam_hat_of(L)
+    rng = np.random.default_rng(3)
+    mu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 500, rng) for _ in range(B)], axis=1))
+    nu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 500, rng) for _ in range(B)], axis=1))
+    plan = gs.Plan(g, K, B)
+    ok = gs.gs_sinkhorn(plan, lam, t, mu, nu, J, want_floors=True)
+    assert ok["n_floored"] == 0
+    bad = gs.gs_sinkhorn(plan, lam / 30, t, mu, nu, J, want_floors=True)
+    assert bad["n_floored"] > 0

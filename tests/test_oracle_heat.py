@@ -116,3 +116,31 @@ def test_underestimated_lambda_breaks_expansion():
     bad = heat.heat_apply(L, 0.1 * lmax, t, K, x) - heat.heat_dense_exact(L, 0.1 * lmax, t) @ x
     assert np.linalg.norm(good) < 1e-12
     assert np.linalg.norm(bad) > 1e-3
+
+
+def test_lambda_hat_below_the_spectrum_voids_the_truncation_bound():
+    """The rescaling needs lambda_hat >= lambda_max.  Below it, eigenvalues of
+    y = (2/lambda_hat) L - I exceed 1, where |T_k(y)| = cosh(k acosh y) > 1:
+    the series still expands the entire function exp(-t(y+1)), but the tail
+    sum_{k>K} |b_k| no longer bounds the truncation error against
+    exp(-t L_op), and once T_K(y_max) outgrows the coefficients' decay the
+    truncated sum blows up (no longer a contraction; exp(-t L_op) has
+    eigenvalues in (0, 1]).  The mass identity 1^T p_K x = p_K(0) 1^T x holds
+    throughout (L 1 = 0 gives y 1 = -1 for every lambda_hat), so it cannot
+    reveal a too-small lambda_hat."""
+    A, L = small_knn()
+    lm = spectrum.lambda_max(L)
+    t, K = 8.0, 20
+    b = heat.cheb_coeffs(t, K)
+    p0 = b[0] / 2 + sum((-1) ** k * b[k] for k in range(1, K + 1))
+    tail = heat.tail_bound(t, K)
+    x = np.random.default_rng(4).standard_normal(L.shape[0])
+    nx = np.linalg.norm(x)
+    for ratio, bounded, contraction in ((1.0, True, True), (1.5, True, True), (0.9, False, True),
+                                        (0.5, False, False)):
+        lam = ratio * lm
+        y = heat.heat_apply(L, lam, t, K, x)
+        err = np.linalg.norm(y - heat.heat_dense_exact(L, lam, t) @ x)
+        assert (err <= tail * nx + 1e-12) == bounded, (ratio, err, tail * nx)
+        assert (np.linalg.norm(y) <= (1 + tail) * nx) == contraction, ratio
+        assert abs(y.sum() - p0 * x.sum()) <= 1e-9 * max(np.abs(y).sum(), 1.0), ratio
