@@ -329,6 +329,7 @@ def main():
     g = gs.gs_graph_from_points(X, args.knn)
     t_graph = time.perf_counter() - t0
     log(f"[setup] kNN graph n={g.n} nnz={g.nnz} components={g.n_components} in {t_graph:.1f}s")
+    inputs = {"points_sha256": synth.sha256(X)}
     del X
     lam = gs.gs_lambda_max(g, iters=60, seed=5, safety=1.01)
     log(f"[setup] lambda_hat={lam:.4f} (edge bound {g.edge_bound:.4f})")
@@ -344,6 +345,17 @@ def main():
     H = {i: synth.histogram_on_random_support(n, int(sizes[i]), 1.0, synth.seed_for(5, 2) * 1000 + i)
          for i in need}
     Hd = {i: torch.from_numpy(h).to(dev) for i, h in H.items()}
+    hh = hashlib.sha256()
+    for i in need:
+        hh.update(synth.sha256(H[i]).encode())
+    rp_, col_, w_, _ = g.export()
+    inputs.update({"csr_sha256": hashlib.sha256(synth.sha256(rp_).encode() + synth.sha256(col_).encode()
+                                                 + synth.sha256(w_).encode()).hexdigest(),
+                   "histograms_sha256": hh.hexdigest(), "histograms": len(need),
+                   "seeds": {"points": synth.seed_for(5, 0), "surface": synth.seed_for(5, 1),
+                             "support_sizes": synth.seed_for(5, 2), "pair_order": synth.seed_for(5, 3),
+                             "histogram_i": f"{synth.seed_for(5, 2)} * 1000 + i", "lambda_max": 5}})
+    del rp_, col_, w_
     del H
     dev_batches = []
     for b in batches:
@@ -551,6 +563,7 @@ def main():
         "graph_build_s": round(t_graph, 2),
         "other_workloads": extras,
         "results_finite": bool(finite),
+        "inputs": inputs,
     }
     print(json.dumps(line), flush=True)
 
