@@ -6,7 +6,10 @@
  * exp(-t (2/lambda_hat) L) x is a discrete Fourier transform away; p_K differs
  * from it by at most the Chebyshev tail bound per eigenvalue (2-norm).  Two
  * adjacent Diracs: the only coupling moves the unit mass along one edge, and
- * after one w-update Algorithm 1 returns D = -4t ln H_01.
+ * after one w-update Algorithm 1 returns D = -4t ln H_01.  Also: a negative
+ * histogram entry reported by status, the reverse sweep from recorded
+ * denominators, and two columns summed into one distribution by
+ * gs_accumulate_columns.
  * Exit status 0 on success, 1 on a failed check, 77 without a device. */
 #include <math.h>
 #include <stdio.h>
@@ -145,6 +148,53 @@ int main(void) {
         if (!(fabs(dist[c] - dref) <= tol)) FAIL("distance %d: %.9g vs %.9g", c, dist[c], dref);
     }
     if (nfl != 0) FAIL("unexpected floors: %lld", (long long)nfl);
+
+    /* a negative histogram entry is reported at the call's synchronisation */
+    hmu[7 * B + 1] = -0.25f;
+    HIPCK(hipMemcpy(dmu, hmu, sizeof(float) * n * B, hipMemcpyHostToDevice));
+    double dbad[2];
+    if (gs_sinkhorn(p, lam_hat, t, NULL, dmu, dnu, 5, 1e-30f, 0, NULL, NULL, NULL, dbad, NULL, NULL, 0) !=
+            GS_ERR_INVALID || strstr(gs_last_error(), "negative") == NULL)
+        FAIL("negative histogram entry not reported: %s", gs_last_error());
+    hmu[7 * B + 1] = 0.0f;
+    HIPCK(hipMemcpy(dmu, hmu, sizeof(float) * n * B, hipMemcpyHostToDevice));
+
+    /* reverse sweep from recorded denominators (finite gradients), and the
+     * accumulation of both columns of a known n x 2 block (the heat test's
+     * input) into distribution 0 of a 2 x n gradient, in column order */
+    const int J = 5, ldp = 4;   /* B = 2 rounds up to a padded row of 4 floats */
+    float *drec = NULL, *dgmu = NULL, *dG = NULL;
+    int32_t* dcols = NULL;
+    HIPCK(hipMalloc((void**)&drec, sizeof(float) * 2 * J * (size_t)n * ldp));
+    HIPCK(hipMalloc((void**)&dgmu, sizeof(float) * n * B));
+    HIPCK(hipMalloc((void**)&dG, sizeof(float) * 2 * n));
+    HIPCK(hipMalloc((void**)&dcols, sizeof(int32_t) * B));
+    HIPCK(hipMemset(dG, 0, sizeof(float) * 2 * n));
+    const int32_t hcols[2] = {0, 0};
+    HIPCK(hipMemcpy(dcols, hcols, sizeof(hcols), hipMemcpyHostToDevice));
+    GS(gs_sinkhorn(p, lam_hat, t, NULL, dmu, dnu, J, 1e-30f, GS_RECORD_ALL, drec, NULL, NULL, dist, NULL, NULL, 0));
+    const double ones[2] = {1.0, 1.0};
+    double gt[2] = {0.0, 0.0};
+    GS(gs_sinkhorn_backward(p, lam_hat, t, NULL, dmu, dnu, J, 1e-30f, GS_RECORD_ALL, drec, ones, dgmu, NULL, gt, 0));
+    GS(gs_accumulate_columns(dx, n, B, dcols, 2, dG, 0));
+    HIPCK(hipDeviceSynchronize());
+    float* hg = malloc(sizeof(float) * n * B);
+    float* hG = malloc(sizeof(float) * 2 * n);
+    HIPCK(hipMemcpy(hg, dgmu, sizeof(float) * n * B, hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(hG, dG, sizeof(float) * 2 * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n * B; ++i)
+        if (!isfinite(hg[i])) FAIL("non-finite gradient at %d", i);
+    if (!isfinite(gt[0]) || !isfinite(gt[1])) FAIL("non-finite gradient in t");
+    for (int i = 0; i < n; ++i) {
+        const float want = (0.0f + hx[i * B]) + hx[i * B + 1];
+        if (hG[i] != want || hG[n + i] != 0.0f) FAIL("accumulated column at node %d: %g vs %g", i, hG[i], want);
+    }
+    HIPCK(hipFree(drec));
+    HIPCK(hipFree(dgmu));
+    HIPCK(hipFree(dG));
+    HIPCK(hipFree(dcols));
+    free(hg);
+    free(hG);
 
     gs_plan_destroy(p);
     gs_graph_destroy(g);
