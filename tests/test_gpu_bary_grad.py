@@ -202,3 +202,38 @@ def test_autograd_function(gs, clusters, ce):
     got = to_host(mud.grad).reshape(n, B)
     assert np.linalg.norm(got[s] - ref["dmu"][s]) / np.linalg.norm(ref["dmu"][s]) <= 1e-4
     assert tt.grad.item() == pytest.approx(ref["dt"].sum(), rel=1e-4)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+@pytest.mark.parametrize("ce", [2, -1])
+def test_smallest_degrees_forward_and_backward(gs, clusters, K, ce):
+    """K = 1 (the first step is also the last: scaling epilogue and record
+    store on it), K = 2 and 3 (one flush before the last step), forward and
+    reverse sweep (the dual form on those schedules) against the oracle.
+    At t = 0.3 with dense positive histograms every denominator stays above
+    the floor (asserted), so both sides take the same branches."""
+    n, labels, arrs, L = clusters
+    B, t, J = 3, 0.3, 6
+    rng = np.random.default_rng(K * 10 + ce)
+    mu = synth.random_dense_like(n, B, rng, positive=True)
+    nu = synth.random_dense_like(n, B, rng, positive=True)
+    mu /= mu.sum(axis=0)
+    nu /= nu.sum(axis=0)
+    gd = np.array([1.0, -0.5, 2.0])
+    lam = lam_hat_of(L)
+    ref = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, g=gd)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    mud, nud = to_dev(mu), to_dev(nu)
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=ce, ckpt=ckpt, want_floors=True)
+    assert out["n_floored"] == 0
+    assert (np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)).all(), (out["dist"], ref["D"])
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, gd, grad_mu=gmu, grad_nu=gnu)
+    for got, want in ((to_host(gmu).reshape(n, B), ref["dmu"]), (to_host(gnu).reshape(n, B), ref["dnu"])):
+        for b in range(B):
+            rel = np.linalg.norm(got[:, b] - want[:, b]) / np.linalg.norm(want[:, b])
+            assert rel <= 1e-4, (K, b, rel)
+    np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
