@@ -58,6 +58,23 @@ def test_graph_from_points_clusters_r50(gs):
     assert g.n_components == info["n_components"]
 
 
+@pytest.mark.parametrize("shape,k", [((32, 32), 10), ((10, 10, 10), 20), ((10, 10, 10), 27)])
+def test_graph_from_points_exact_ties_on_integer_lattices(gs, shape, k):
+    """Integer lattices (d = 2, 3): every float32 Gram distance is exact, so
+    neighbours tie in whole shells (4, 8, 12 or 24 points at one distance);
+    the graph must follow the lower-id rule exactly as the oracle does, also
+    where a shell straddles the k-th place."""
+    grids = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    X = np.stack([g.ravel() for g in grids], axis=1).astype(np.float32)
+    (rp, col, w32), L, info, A = oracle_csr(X, k)
+    g = gs.gs_graph_from_points(X, k)
+    grp, gcol, gw, _ = g.export()
+    np.testing.assert_array_equal(grp, rp)
+    np.testing.assert_array_equal(gcol, col)
+    np.testing.assert_allclose(gw, A.data, rtol=2 * 2.0 ** -24, atol=0)
+    assert g.median == pytest.approx(info["median"], rel=1e-12)
+
+
 def test_lambda_max_bounds(gs, swiss):
     X, arrs, L, info, A = swiss
     g = gs.gs_graph_from_csr(2000, *arrs)
