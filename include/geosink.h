@@ -83,7 +83,9 @@ int32_t gs_abi_version(void);
  * Edges are the union of the directed k-nearest-neighbour relations (self
  * excluded, equal distances broken towards the lower node id); the weight of
  * edge {i,j} is exp(-|x_i - x_j|^2 / m^2) with m the median of the n*k
- * directed neighbour distances.  Candidate neighbours are found on the GPU
+ * directed neighbour distances (GS_ERR_INVALID when m = 0, i.e. more than
+ * half of the directed pairs are duplicate points; duplicates below that get
+ * weight 1).  Candidate neighbours are found on the GPU
  * (float32 Gram tiles, k+8 candidates per point) and ranked on the host in
  * float64 by exact squared distance.  Device CSR (int32 row pointers and
  * column ids, float32 weights) stays resident in the returned handle.

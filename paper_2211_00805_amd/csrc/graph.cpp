@@ -158,6 +158,11 @@ void build_graph_from_points(const float* X, int64_t n, int d, int k, hipStream_
         const double lo = *std::max_element(dist.begin(), dist.begin() + N / 2);
         med = (lo + med) / 2.0;
     }
+    // m = 0 (more than half of the directed neighbour pairs coincide) leaves
+    // exp(-d^2 / m^2) undefined on the coincident pairs
+    if (!(med > 0.0))
+        fail(GS_ERR_INVALID, "the median neighbour distance is 0 (over half of the kNN pairs are duplicate points): "
+                             "the Gaussian weights exp(-d^2/m^2) are undefined");
     const double m2 = med * med;
 
     // union of directed edges, rows sorted by column, duplicates merged

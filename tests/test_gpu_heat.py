@@ -75,6 +75,27 @@ def test_graph_from_points_exact_ties_on_integer_lattices(gs, shape, k):
     assert g.median == pytest.approx(info["median"], rel=1e-12)
 
 
+def test_graph_from_points_with_duplicate_points(gs):
+    """Some duplicated points (distance 0, weight exp(0) = 1, ties to the lower
+    id) match the oracle; a cloud whose median neighbour distance is 0 (every
+    point repeated 12 times, k = 10) is refused, since exp(-d^2 / m^2) is then
+    undefined."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((300, 5)).astype(np.float32)
+    X = np.concatenate([X, X[rng.choice(300, 40, replace=False)]])
+    (rp, col, w32), L, info, A = oracle_csr(X, 8)
+    assert info["median"] > 0 and np.any(info["directed_dist"] == 0)
+    g = gs.gs_graph_from_points(X, 8)
+    grp, gcol, gw, _ = g.export()
+    np.testing.assert_array_equal(grp, rp)
+    np.testing.assert_array_equal(gcol, col)
+    np.testing.assert_allclose(gw, A.data, rtol=2 * 2.0 ** -24, atol=0)
+    dup = np.repeat(rng.standard_normal((50, 5)).astype(np.float32), 12, axis=0)
+    with pytest.raises(gs.GeoSinkError) as e:
+        gs.gs_graph_from_points(dup, 10)
+    assert e.value.status == -1 and "median" in str(e.value)
+
+
 def test_lambda_max_bounds(gs, swiss):
     X, arrs, L, info, A = swiss
     g = gs.gs_graph_from_csr(2000, *arrs)
