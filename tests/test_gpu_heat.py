@@ -96,6 +96,22 @@ def test_graph_from_points_with_duplicate_points(gs):
     assert e.value.status == -1 and "median" in str(e.value)
 
 
+@pytest.mark.parametrize("n,k,d", [(2, 1, 3), (20, 19, 3), (131, 32, 7)])
+def test_graph_from_points_tiny_and_complete(gs, n, k, d):
+    """Fewer points than one 128-point tile, k = n - 1 (the complete graph:
+    fewer other points than the k + 8 candidate slots), the largest k, an
+    odd dimension: the same CSR as the oracle."""
+    X = np.random.default_rng(n + k).standard_normal((n, d)).astype(np.float32)
+    (rp, col, w32), L, info, A = oracle_csr(X, k)
+    g = gs.gs_graph_from_points(X, k)
+    grp, gcol, gw, _ = g.export()
+    np.testing.assert_array_equal(grp, rp)
+    np.testing.assert_array_equal(gcol, col)
+    np.testing.assert_allclose(gw, A.data, rtol=2 * 2.0 ** -24, atol=0)
+    if k == n - 1:
+        assert len(gcol) == n * (n - 1)
+
+
 def test_lambda_max_bounds(gs, swiss):
     X, arrs, L, info, A = swiss
     g = gs.gs_graph_from_csr(2000, *arrs)
