@@ -9,7 +9,7 @@
   * the smallest graph, one edge: heat applications against the two-node
     closed form, the Dirac-to-Dirac distance against -4t ln H_12 and against
     the hand-derived golden values within the truncation bound;
-  * a wide batch, B = 1024 columns;
+  * wide batches, B = 1024 and the largest plan width B = 4096;
   * negative or non-finite histogram and vertex-weight entries: reported by
     status at the call's synchronisation, the plan unaffected;
   * a distance that overflows float32: GS_ERR_NONFINITE; a lambda_hat far
@@ -132,6 +132,32 @@ def test_wide_batch(gs, swiss):
     cols = [0, 1, 511, 1000, 1023]
     ref = heat.heat_apply(L, lam, t, K, x[:, cols].astype(np.float64))
     assert np.abs(to_host(Y).reshape(n, B)[:, cols] - ref).max() <= heat_tol(K, np.abs(x).max())
+
+
+def test_largest_batch(gs, swiss):
+    """B = 4096, the largest plan width: heat application on sampled columns
+    (both ends of the batch) and Algorithm 1's distances on sampled pairs
+    against the oracle."""
+    arrs, L = swiss
+    n, K, t, B, J = 2000, 8, 1.0, 4096, 3
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    x = synth.random_dense_like(n, B, np.random.default_rng(13))
+    Y = torch.empty(n * B, device="cuda")
+    gs.gs_heat_apply(plan, lam, t, to_dev(x), Y)
+    cols = [0, 1, 2047, 4094, 4095]
+    ref = heat.heat_apply(L, lam, t, K, x[:, cols].astype(np.float64))
+    assert np.abs(to_host(Y).reshape(n, B)[:, cols] - ref).max() <= heat_tol(K, np.abs(x).max())
+    rng = np.random.default_rng(14)
+    mu = synth.random_dense_like(n, B, rng, positive=True)
+    nu = synth.random_dense_like(n, B, rng, positive=True)
+    mu /= mu.sum(axis=0)
+    nu /= nu.sum(axis=0)
+    D = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J)["dist"]
+    Dref = sinkhorn.sinkhorn(L, lam, t, K, mu[:, cols].astype(np.float64), nu[:, cols].astype(np.float64), J,
+                             marginals=False)["D"]
+    assert np.all(np.abs(D[cols] - Dref) <= 1e-5 * np.maximum(np.abs(Dref), 4 * t)), (D[cols], Dref)
 
 
 def test_negative_and_non_finite_inputs_are_reported(gs, swiss):
