@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import synth
+from oracle import heat
 from oracle import sinkhorn as osk
 from gpu_common import lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
 
@@ -82,6 +83,29 @@ def test_barycenter_single_input_is_smoothed_input(gs, clusters):
     bary = torch.empty(n, device="cuda")
     gs.gs_barycenter(plan, lam, t, to_dev(H), [1.0], 3, bary)
     assert np.abs(to_host(bary) - ref["p"]).sum() <= 1e-6
+
+
+def test_barycenter_one_hot_weights_ignore_the_other_inputs(gs, clusters):
+    """alpha = e_2 among m = 5 inputs: p = q_2 after one iteration, w_2 = 1,
+    so p stays p_K mu_2 / p_K(0) (the single-input closed form) whatever the
+    other inputs are; also against the oracle's iteration."""
+    n, labels, arrs, L = clusters
+    m, K, t, J = 5, 30, 1.0, 4
+    rng = np.random.default_rng(18)
+    H, _ = synth.loguniform_support_histograms(n, m, 100, 400, 1.0, rng)
+    alpha = np.zeros(m)
+    alpha[2] = 1.0
+    lam = lam_hat_of(L)
+    ref = osk.barycenter(L, lam, t, K, H.astype(np.float64), alpha, J)
+    b = heat.cheb_coeffs(t, K)
+    p0 = b[0] / 2 + sum((-1) ** k * b[k] for k in range(1, K + 1))
+    closed = heat.heat_apply(L, lam, t, K, H[:, 2].astype(np.float64)) / p0
+    assert np.abs(ref["p"] - closed).sum() <= 1e-12
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, m)
+    bary = torch.empty(n, device="cuda")
+    gs.gs_barycenter(plan, lam, t, to_dev(H), alpha, J, bary)
+    assert np.abs(to_host(bary) - closed).sum() <= 1e-6
 
 
 def _grad_case(n, labels, B, rng):
