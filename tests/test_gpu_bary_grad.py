@@ -149,14 +149,18 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
+@pytest.mark.parametrize("zeros", [False, True])
 @pytest.mark.parametrize("ce", [7, -1])
-def test_backward_with_vertex_weights_matches_oracle(gs, clusters, ce):
-    """Vertex weights a (R7) through forward and reverse sweep, checkpointed and recorded."""
+def test_backward_with_vertex_weights_matches_oracle(gs, clusters, ce, zeros):
+    """Vertex weights a (R7) through forward and reverse sweep, checkpointed and
+    recorded; also with a = 0 on a tenth of the nodes (allowed: a >= 0)."""
     n, labels, arrs, L = clusters
     B, K, t, J = 3, 30, 1.5, 15
     rng = np.random.default_rng(55)
     mu, nu = _grad_case(n, labels, B, rng)
     a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    if zeros:
+        a[rng.choice(n, n // 10, replace=False)] = 0.0
     lam = lam_hat_of(L)
     gd = np.array([1.0, -0.7, 0.4])
     ref = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J,
