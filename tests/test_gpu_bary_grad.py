@@ -15,7 +15,7 @@ import torch
 import synth
 from oracle import heat
 from oracle import sinkhorn as osk
-from gpu_common import lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
+from gpu_common import csr_laplacian, lam_hat_of, need_gpu, oracle_csr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -106,6 +106,43 @@ def test_barycenter_one_hot_weights_ignore_the_other_inputs(gs, clusters):
     bary = torch.empty(n, device="cuda")
     gs.gs_barycenter(plan, lam, t, to_dev(H), alpha, J, bary)
     assert np.abs(to_host(bary) - closed).sum() <= 1e-6
+
+
+@pytest.mark.parametrize("B", [1, 6])
+def test_hub_rows_forward_and_backward(gs, B):
+    """Rows with 1500-2900 nonzeros run in the long-row blocks: Algorithm 1's
+    scaling epilogue (the floor counter runs over a partial wave; supports on
+    a third of the nodes leave nothing to floor, as in the oracle) and the
+    dual adjoint step there, against the oracle."""
+    n, K, t, J = 6000, 12, 1.0, 4
+    arrs = synth.random_local_graph(n, 6, 300, np.random.default_rng(21), hubs=4, hub_degree=2900)
+    assert np.diff(arrs[0]).max() > 1500
+    L = csr_laplacian(n, arrs)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = g.edge_bound
+    rng = np.random.default_rng(30 + B)
+    mu = synth.random_dense_like(n, B, rng, positive=True) * (rng.uniform(size=(n, B)) < 0.33)
+    nu = synth.random_dense_like(n, B, rng, positive=True) * (rng.uniform(size=(n, B)) < 0.33)
+    mu /= mu.sum(axis=0)
+    nu /= nu.sum(axis=0)
+    gd = np.linspace(1.0, 2.0, B)
+    ref = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, g=gd)
+    fl = osk.sinkhorn(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, marginals=False)["n_floored"]
+    plan = gs.Plan(g, K, B)
+    mud, nud = to_dev(mu), to_dev(nu)
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, gs.GS_RECORD_ALL), device="cuda")
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=gs.GS_RECORD_ALL, ckpt=ckpt, want_floors=True)
+    assert out["n_floored"] == fl
+    assert (np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)).all(), (out["dist"], ref["D"])
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, gs.GS_RECORD_ALL, ckpt, gd, grad_mu=gmu, grad_nu=gnu)
+    for got, want, h in ((to_host(gmu).reshape(n, B), ref["dmu"], mu), (to_host(gnu).reshape(n, B), ref["dnu"], nu)):
+        for b in range(B):
+            s_ = h[:, b] > 0
+            rel = np.linalg.norm(got[s_, b] - want[s_, b]) / np.linalg.norm(want[s_, b])
+            assert rel <= 1e-4, (b, rel)
+    np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
 def _grad_case(n, labels, B, rng):
