@@ -145,6 +145,41 @@ def test_hub_rows_forward_and_backward(gs, B):
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
+def test_hub_row_floors_are_counted(gs):
+    """A floored hub row: a local banded graph plus one hub (2005 nonzeros,
+    a long-row block) linked to nodes 3000-4999, mu around the hub, nu on
+    nodes 0-50, K = 5: every denominator on either support is a structural
+    zero after the first v-update, so the counts (long-row and ordinary
+    blocks, partial-wave ballots) must equal the oracle's exactly, and D its
+    floor value."""
+    import scipy.sparse as sp
+    n, hub, B, K, t, J = 6000, 5000, 2, 5, 1.0, 3
+    rp, col, w = synth.random_local_graph(n, 3, 10, np.random.default_rng(40))
+    A = sp.csr_matrix((w.astype(np.float64), col, rp), shape=(n, n))
+    nb = np.arange(3000, 5000)
+    H = sp.coo_matrix((np.full(len(nb), 0.5), (np.full(len(nb), hub), nb)), shape=(n, n))
+    A2 = (A + H + H.T).tocsr()
+    A2.sort_indices()
+    arrs = (A2.indptr.astype(np.int32), A2.indices.astype(np.int32), A2.data.astype(np.float32))
+    assert np.diff(arrs[0])[hub] > 1500
+    L = csr_laplacian(n, arrs)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = g.edge_bound
+    rng = np.random.default_rng(41)
+    mu = np.zeros((n, B), dtype=np.float32)
+    nu = np.zeros((n, B), dtype=np.float32)
+    mu[4990:5011] = rng.uniform(0.1, 1.0, (21, B))
+    nu[0:51] = rng.uniform(0.1, 1.0, (51, B))
+    mu /= mu.sum(axis=0)
+    nu /= nu.sum(axis=0)
+    ref = osk.sinkhorn(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, marginals=False)
+    assert ref["n_floored"] == B * ((J - 1) * 21 + J * 51)
+    plan = gs.Plan(g, K, B)
+    out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, want_floors=True)
+    assert out["n_floored"] == ref["n_floored"]
+    assert (np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)).all(), (out["dist"], ref["D"])
+
+
 def _grad_case(n, labels, B, rng):
     mus, nus = [], []
     for b in range(B):
