@@ -98,3 +98,23 @@ def test_expected_barycenter_effect_recovers_the_shift(gs, shift, n_comp):
     assert abs(tau - 5.0) < 0.05, tau
     if shift != 5.0:
         assert abs(tau - 5.0) < abs(naive - 5.0), (tau, naive)
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (999, 3), (100003, 257), (5000, 4096)])
+def test_expectation_matches_float64(gs, n, d):
+    """gs_expectation over one or many column tiles (d up to 4096 features),
+    ragged n, a single node: float64 products and fixed-order sums, so within
+    1e-12 of the float64 weighted mean of the same float32 inputs; a signal of
+    zero mass is refused with GS_ERR_NONFINITE."""
+    rng = np.random.default_rng(n + d)
+    p = (rng.uniform(0.0, 1.0, n) * (rng.uniform(size=n) < 0.5)).astype(np.float32)
+    p[0] = 0.75
+    Y = rng.standard_normal((n, d)).astype(np.float32)
+    got = gs.gs_expectation(to_dev(p), to_dev(Y))
+    p64, Y64 = p.astype(np.float64), Y.astype(np.float64)
+    ref = (p64 @ Y64) / p64.sum()
+    scale = (p64 @ np.abs(Y64)) / p64.sum()
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300), np.abs(got - ref).max()
+    with pytest.raises(gs.GeoSinkError) as e:
+        gs.gs_expectation(torch.zeros(n, device="cuda"), to_dev(Y))
+    assert e.value.status == -6
