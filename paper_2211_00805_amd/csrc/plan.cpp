@@ -3,13 +3,17 @@
 // autotuner and hipGraph capture of whole iterations.
 #include "plan.h"
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <functional>
 #include <fstream>
 #include <initializer_list>
 #include <memory>
 #include <sstream>
+#include <thread>
 #include <utility>
 
 namespace gs {
@@ -126,13 +130,27 @@ std::map<std::string, std::string> read_cache(const std::string& path) {
     return m;
 }
 
+// Written to a private temporary file and renamed over the cache, so that
+// processes or threads tuning at the same time never leave a mixed file
+// (the last rename wins; a cache that cannot be written is not an error).
 void write_cache(const std::string& path, const std::map<std::string, std::string>& m) {
-    std::ofstream f(path, std::ios::trunc);
-    if (!f) return;  // a cache that cannot be written is not an error
-    f << "{\n";
-    size_t i = 0;
-    for (const auto& kv : m) f << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++i < m.size() ? ",\n" : "\n");
-    f << "}\n";
+    const std::string tmp = path + ".tmp." + std::to_string((long long)getpid()) + "." +
+                            std::to_string(std::hash<std::thread::id>{}(std::this_thread::get_id()));
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return;
+        f << "{\n";
+        size_t i = 0;
+        for (const auto& kv : m)
+            f << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++i < m.size() ? ",\n" : "\n");
+        f << "}\n";
+        if (!f) {
+            f.close();
+            std::remove(tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
 }
 
 double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>& be) {
