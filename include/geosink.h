@@ -329,7 +329,7 @@ gs_status gs_accumulate_columns(const float* src, int64_t n, int32_t B, const in
  * launch: per step the CSR once (4(n+1) + 8 nnz), T_{k-1} once (4nB, the
  * gathered operand), T_{k-2} (4nB, all steps but the first), T_k (4nB, all
  * steps but the last) and the accumulator (4nB read and/or written on every
- * third step and on the last).  Synchronises `stream`. */
+ * third step and on the last).  1 <= reps <= 100000.  Synchronises `stream`. */
 gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms,
                             double* bytes_per_launch);
 

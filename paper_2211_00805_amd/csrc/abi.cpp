@@ -322,7 +322,7 @@ gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, h
 gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms, double* bytes_per_launch) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr && avg_ms != nullptr, "plan / avg_ms is NULL");
-        GS_REQUIRE(reps >= 1, "reps must be >= 1");
+        GS_REQUIRE(reps >= 1 && reps <= 100000, "reps must be in [1, 100000]");
         *avg_ms = time_step(*p, p->shape, reps, stream, bytes_per_launch);
     });
 }

@@ -91,6 +91,12 @@ def test_validation_rejects_before_any_device_call():
     assert lib.gs_plan_set_kernel(None, 1, 4, 0) == -1
     assert b"plan is NULL" in lib.gs_last_error()
     assert lib.gs_expectation(None, None, 10, 1, None, None) == -1
+    ms, by = C.c_double(), C.c_double()
+    assert lib.gs_plan_time_step(None, 10, None, C.byref(ms), C.byref(by)) == -1
+    assert lib.gs_stream_copy(None, None, 4, None) == -1
+    assert lib.gs_stream_gather(None, 10, None, 4, None, None) == -1
+    assert lib.gs_accumulate_columns(None, 10, 4, None, 2, None, None) == -1
+    assert b"NULL" in lib.gs_last_error()
 
 
 def test_abi_version():
