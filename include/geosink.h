@@ -299,6 +299,17 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
 gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, hipStream_t stream,
                          double* out);
 
+/* A batch's mu (or nu) block from a set of m distributions (the pairs of the
+ * Sec. "Nearest-Wasserstein-neighbor distributions" experiment):
+ * out[i*B + b] = H[i*m + cols[b]].
+ *   H     device n x m float32, node-major (distribution c is column c).
+ *   cols  device B int32: the distribution of each batch column; entries
+ *         outside [0, m) give a zero column.
+ *   out   device n x B float32 (a gs_sinkhorn input), must not overlap H.
+ *   1 <= n < 2^31, m >= 1, 1 <= B <= 4096.  Asynchronous; allocates nothing. */
+gs_status gs_gather_columns(const float* H, int64_t n, int32_t m, const int32_t* cols, int32_t B, float* out,
+                            hipStream_t stream);
+
 /* Per-distribution gradients from a batch's per-pair gradients.  When the B
  * pairs of a gs_sinkhorn batch draw their columns from m distributions (all
  * pairs of the Sec. "Nearest-Wasserstein-neighbor distributions" experiment),

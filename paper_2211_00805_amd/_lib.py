@@ -71,6 +71,7 @@ _SIGS = {
     "gs_plan_time_step": (C.c_int, [c_plan, C.c_int32, c_stream, P_f64, P_f64]),
     "gs_stream_copy": (C.c_int, [P_f32, P_f32, C.c_int64, c_stream]),
     "gs_stream_gather": (C.c_int, [P_f32, C.c_int64, P_i32, C.c_int64, P_f32, c_stream]),
+    "gs_gather_columns": (C.c_int, [P_f32, C.c_int64, C.c_int32, P_i32, C.c_int32, P_f32, c_stream]),
     "gs_accumulate_columns": (C.c_int, [P_f32, C.c_int64, C.c_int32, P_i32, C.c_int32, P_f32, c_stream]),
 }
 

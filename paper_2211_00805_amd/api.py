@@ -22,7 +22,7 @@ __all__ = [
     "GS_RECORD_ALL", "ckpt_floats",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
-    "gs_barycenter", "gs_expectation", "gs_accumulate_columns", "gs_plan_time_step", "gs_stream_copy", "gs_stream_gather", "current_stream",
+    "gs_barycenter", "gs_expectation", "gs_gather_columns", "gs_accumulate_columns", "gs_plan_time_step", "gs_stream_copy", "gs_stream_gather", "current_stream",
 ]
 
 
@@ -276,6 +276,18 @@ def gs_expectation(p: torch.Tensor, Y: torch.Tensor) -> np.ndarray:
     check("gs_expectation", lib.gs_expectation(_dev(p, "p"), _dev(Y, "Y"), n, d, current_stream(),
                                                out.ctypes.data_as(_lib.P_f64)))
     return out
+
+
+def gs_gather_columns(H: torch.Tensor, cols: torch.Tensor, out: torch.Tensor) -> None:
+    """out[:, b] = H[:, cols[b]] for H (n, m), cols (B,) int32 on the device, out (n, B); cols outside [0, m) give 0."""
+    if H.dim() != 2 or out.dim() != 2 or out.shape[0] != H.shape[0]:
+        raise ValueError("H must be (n, m) and out (n, B)")
+    if cols.dtype != torch.int32 or cols.device.type != "cuda" or not cols.is_contiguous() or \
+            cols.numel() != out.shape[1]:
+        raise TypeError("cols must be a contiguous int32 device tensor with B entries")
+    check("gs_gather_columns", lib.gs_gather_columns(
+        _dev(H, "H"), H.shape[0], H.shape[1], C.c_void_p(cols.data_ptr()), out.shape[1], _dev(out, "out"),
+        current_stream()))
 
 
 def gs_accumulate_columns(src: torch.Tensor, cols: torch.Tensor, G: torch.Tensor) -> None:

@@ -335,6 +335,19 @@ gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_
     });
 }
 
+gs_status gs_gather_columns(const float* H, int64_t n, int32_t m, const int32_t* cols, int32_t B, float* out,
+                            hipStream_t stream) {
+    return guarded([&] {
+        GS_REQUIRE(H != nullptr && cols != nullptr && out != nullptr, "H / cols / out is NULL");
+        GS_REQUIRE(n >= 1 && n < (int64_t)1 << 31, "n must be in [1, 2^31)");
+        GS_REQUIRE(m >= 1, "m must be >= 1");
+        GS_REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+        GS_REQUIRE((const float*)out != H, "H and out must not overlap");
+        launch_gather_columns(H, n, m, cols, B, out, stream);
+        GS_HIP(hipGetLastError());
+    });
+}
+
 gs_status gs_accumulate_columns(const float* src, int64_t n, int32_t B, const int32_t* cols, int32_t m, float* G,
                                 hipStream_t stream) {
     return guarded([&] {

@@ -1,3 +1,9 @@
+// Moving columns between a set of m distributions and a batch of B pairs.
+//
+// Gather: a batch's mu (or nu) block takes column cols[b] of the node-major
+// n x m distribution matrix H, out[i*B + b] = H[i*m + cols[b]]; one thread
+// per output element, consecutive threads write consecutive elements.
+//
 // Per-distribution gradients from per-pair gradients.  When B pairs of a
 // batch take their sources (or targets) from a set of m distributions, the
 // gradient of a sum of the pairs' distances with respect to distribution c is
@@ -51,7 +57,24 @@ __global__ __launch_bounds__(kNodes) void accumulate_columns_kernel(const float*
     }
 }
 
+__global__ __launch_bounds__(256) void gather_columns_kernel(const float* __restrict__ H, int64_t n, int m,
+                                                             const int32_t* __restrict__ cols, int B,
+                                                             float* __restrict__ out) {
+    const int64_t total = n * B;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / B;
+        const int c = cols[e - i * B];
+        out[e] = (c >= 0 && c < m) ? H[i * m + c] : 0.f;
+    }
+}
+
 }  // namespace
+
+void launch_gather_columns(const float* H, int64_t n, int m, const int32_t* cols, int B, float* out, hipStream_t st) {
+    int64_t blocks = (n * B + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(gather_columns_kernel, dim3((unsigned)blocks), dim3(256), 0, st, H, n, m, cols, B, out);
+}
 
 void launch_accumulate_columns(const float* src, int64_t n, int B, const int32_t* cols, int m, float* G,
                                hipStream_t st) {

@@ -199,6 +199,9 @@ void launch_gather_rows(const float* X, int64_t n, const int32_t* idx, int64_t m
 // bad[0] += non-finite entries of x[0, count), bad[1] += negative ones (validate.hip)
 void launch_count_invalid(const float* x, int64_t count, unsigned long long* bad, hipStream_t st);
 
+// out[i*B + b] = H[i*m + cols[b]] (0 for cols[b] outside [0, m)) (accumulate.hip)
+void launch_gather_columns(const float* H, int64_t n, int m, const int32_t* cols, int B, float* out, hipStream_t st);
+
 // G[cols[b]*n + i] += src[i*B + b] for cols[b] in [0, m), b = 0..B-1 in order (accumulate.hip)
 void launch_accumulate_columns(const float* src, int64_t n, int B, const int32_t* cols, int m, float* G,
                                hipStream_t st);

@@ -7,7 +7,8 @@ off-diagonal distances with ground-truth distances, and by the precision at 5
 of each distribution's nearest neighbours.
 
 `distance_matrix` runs the pairs i < j through one plan, B pairs per batch
-(each batch one `gs_sinkhorn` call: B right-hand sides per step launch), with
+(each batch's columns gathered from H by `gs_gather_columns`, then one
+`gs_sinkhorn` call: B right-hand sides per step launch), with
 B = `batch` (or the next power of two above P when there are only P < batch
 pairs); a short last batch is padded with copies of its first pair, whose
 results are dropped.  Widths whose padded row (B rounded up to 4 floats) is a
@@ -24,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .api import (GS_RECORD_ALL, Graph, Plan, ckpt_floats, gs_accumulate_columns, gs_sinkhorn,
+from .api import (GS_RECORD_ALL, Graph, Plan, ckpt_floats, gs_accumulate_columns, gs_gather_columns, gs_sinkhorn,
                   gs_sinkhorn_backward)
 
 
@@ -48,6 +49,8 @@ def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.
     """
     if H.dim() != 2 or H.shape[0] != graph.n:
         raise ValueError(f"H must be (n={graph.n}, m), got {tuple(H.shape)}")
+    if H.dtype != torch.float32 or not H.is_contiguous() or H.device.type != "cuda":
+        raise TypeError("H must be a contiguous float32 device tensor")
     m = H.shape[1]
     pairs = pair_list(m, diagonal)
     D = np.zeros((m, m), dtype=np.float64)
@@ -59,7 +62,8 @@ def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.
         plan = Plan(graph, K, B, flags=plan_flags, tune_cache=tune_cache)
     elif plan.B != B or plan.K != K:
         raise ValueError("plan does not match (K, batch)")
-    Ht = H.t().contiguous()                      # m x n rows: one histogram per row
+    mu = torch.empty((graph.n, B), dtype=torch.float32, device=H.device)
+    nu = torch.empty_like(mu)
     if grad:
         rec = torch.empty(ckpt_floats(plan, iters, GS_RECORD_ALL), dtype=torch.float32, device=H.device)
         gmu = torch.empty((graph.n, B), dtype=torch.float32, device=H.device)
@@ -69,10 +73,8 @@ def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.
         nreal = len(blk)
         if nreal < B:
             blk = np.concatenate([blk, np.repeat(blk[:1], B - nreal, axis=0)])
-        ii = torch.from_numpy(blk[:, 0]).to(H.device)
-        jj = torch.from_numpy(blk[:, 1]).to(H.device)
-        mu = Ht.index_select(0, ii).t().contiguous()
-        nu = Ht.index_select(0, jj).t().contiguous()
+        gs_gather_columns(H, torch.from_numpy(blk[:, 0].astype(np.int32)).to(H.device), mu)
+        gs_gather_columns(H, torch.from_numpy(blk[:, 1].astype(np.int32)).to(H.device), nu)
         if grad:
             d = gs_sinkhorn(plan, lambda_hat, t, mu, nu, iters, phi=phi, ckpt_every=GS_RECORD_ALL,
                             ckpt=rec)["dist"][:nreal]

@@ -144,6 +144,22 @@ def test_accumulate_columns_bit_exact(gs, n, B, m):
     assert np.array_equal(G.cpu().numpy(), _accumulate_reference(src, cols, ref))
 
 
+@pytest.mark.parametrize("n,m,B", [(1, 1, 1), (1000, 7, 37), (70001, 256, 32)])
+def test_gather_columns_bit_exact(gs, n, m, B):
+    """out[:, b] = H[:, cols[b]] with repeated and out-of-range indices (a zero
+    column), ragged sizes, and the benchmark's 256 histograms x 32 pairs."""
+    rng = np.random.default_rng(n + m + B)
+    H = rng.standard_normal((n, m)).astype(np.float32)
+    cols = rng.integers(-1, m + 1, B).astype(np.int32)
+    cols[0] = m - 1
+    if B > 2:
+        cols[1] = cols[2]
+    out = torch.full((n, B), 7.0, device="cuda")
+    gs.gs_gather_columns(to_dev(H), torch.from_numpy(cols).cuda(), out)
+    ref = np.where((cols >= 0) & (cols < m), H[:, np.clip(cols, 0, m - 1)], 0.0).astype(np.float32)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
 def test_accumulate_columns_rejects_bad_arguments(gs):
     src = torch.zeros((8, 4), device="cuda")
     G = torch.zeros((2, 8), device="cuda")
