@@ -49,8 +49,9 @@ def distance_matrix(graph: Graph, lambda_hat: float, t: float, K: int, H: torch.
     """
     if H.dim() != 2 or H.shape[0] != graph.n:
         raise ValueError(f"H must be (n={graph.n}, m), got {tuple(H.shape)}")
-    if H.dtype != torch.float32 or not H.is_contiguous() or H.device.type != "cuda":
-        raise TypeError("H must be a contiguous float32 device tensor")
+    if H.dtype != torch.float32 or H.device.type != "cuda":
+        raise TypeError("H must be a float32 device tensor")
+    H = H.contiguous()
     m = H.shape[1]
     pairs = pair_list(m, diagonal)
     D = np.zeros((m, m), dtype=np.float64)

@@ -53,6 +53,21 @@ def test_distance_matrix_matches_oracle(gs):
         assert np.array_equal(D, D.T)
 
 
+def test_distance_matrix_takes_column_slices(gs):
+    """A non-contiguous column slice of H gives the matrix of its contiguous copy."""
+    per, K, t, J = 40, 20, 2.0, 20
+    X, lab, means = synth.gaussians_on_swiss_roll(15, per)
+    arrs, L, info, A = oracle_csr(X, 10)
+    n = X.shape[0]
+    g = gs.gs_graph_from_csr(n, *arrs)
+    Hd = to_dev(_hists(lab, per, n))
+    sl = Hd[:, 1::3]
+    assert not sl.is_contiguous()
+    D1 = gs.distance_matrix(g, lam_hat_of(L), t, K, sl, J)
+    D2 = gs.distance_matrix(g, lam_hat_of(L), t, K, sl.contiguous(), J)
+    assert np.array_equal(D1, D2)
+
+
 def test_swiss_roll_nearest_neighbour_experiment(gs):
     per, K, t, J = 10000, 50, 2.0, 200
     X, lab, means = synth.gaussians_on_swiss_roll(15, per)
