@@ -36,13 +36,15 @@ class GeoSinkhornDistance(torch.autograd.Function):
         out = gs_sinkhorn(plan, lambda_hat, tval, mu_c, nu_c, iters, phi=phi, a=a, ckpt_every=ckpt_every,
                           ckpt=ckpt)
         ctx.save_for_backward(mu_c, nu_c, ckpt)
-        ctx.cfg = (plan, lambda_hat, tval, iters, ckpt_every, phi, a, isinstance(t, torch.Tensor))
+        t_meta = (t.shape, t.dtype, t.device) if isinstance(t, torch.Tensor) else None
+        ctx.cfg = (plan, lambda_hat, tval, iters, ckpt_every, phi, a, t_meta)
         return torch.as_tensor(out["dist"], device=mu.device)
 
     @staticmethod
     def backward(ctx, grad_D):
         mu, nu, ckpt = ctx.saved_tensors
-        plan, lam, tval, iters, ce, phi, a, t_is_tensor = ctx.cfg
+        plan, lam, tval, iters, ce, phi, a, t_meta = ctx.cfg
+        t_is_tensor = t_meta is not None
         g = np.asarray(grad_D.detach().double().cpu().numpy(), dtype=np.float64).reshape(-1)
         need_mu, need_nu, need_t = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         gmu = torch.empty_like(mu) if need_mu else None
@@ -51,7 +53,8 @@ class GeoSinkhornDistance(torch.autograd.Function):
                                   grad_nu=gnu, want_grad_t=bool(need_t and t_is_tensor))
         grad_t = None
         if need_t and t_is_tensor:
-            grad_t = torch.tensor(float(np.sum(gt)), dtype=torch.float64)
+            # autograd requires t's own device, dtype and shape
+            grad_t = torch.full(t_meta[0], float(np.sum(gt)), dtype=t_meta[1], device=t_meta[2])
         return gmu, gnu, grad_t, None, None, None, None, None, None
 
 

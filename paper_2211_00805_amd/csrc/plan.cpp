@@ -621,6 +621,9 @@ void sinkhorn_backward(gs_plan_s& P, double lam, double t, const float* a, const
     const size_t sz = P.sz();
     if (!P.ACC2.p) P.ACC2.alloc(sz);
     if (P.seg_cap < C) {
+        // captured segment graphs hold the old slot addresses: drop them
+        // before the buffers move
+        drop_graphs(P);
         P.segd.alloc(sz * C);
         P.sege.alloc(sz * C);
         P.seg_cap = C;

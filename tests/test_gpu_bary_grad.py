@@ -304,6 +304,25 @@ def test_autograd_function(gs, clusters, ce):
     assert tt.grad.item() == pytest.approx(ref["dt"].sum(), rel=1e-4)
 
 
+@pytest.mark.parametrize("t_device,t_dtype", [("cuda", torch.float32), ("cpu", torch.float32),
+                                              ("cuda", torch.float64)])
+def test_autograd_time_gradient_keeps_t_device_and_dtype(gs, clusters, t_device, t_dtype):
+    """t given as a device or float32 tensor: its gradient comes back on t's own
+    device with t's dtype and shape (autograd rejects anything else)."""
+    n, labels, arrs, L = clusters
+    B, K, J, t0 = 2, 20, 6, 1.5
+    rng = np.random.default_rng(78)
+    mu, nu = _grad_case(n, labels, B, rng)
+    lam = lam_hat_of(L)
+    ref = osk.sinkhorn_grad(L, lam, t0, K, mu.astype(np.float64), nu.astype(np.float64), J)
+    plan = gs.Plan(gs.gs_graph_from_csr(n, *arrs), K, B)
+    tt = torch.tensor(t0, dtype=t_dtype, device=t_device, requires_grad=True)
+    D = gs.geodesic_sinkhorn_distance(to_dev(mu).view(-1), to_dev(nu).view(-1), tt, plan, lam, J)
+    D.sum().backward()
+    assert tt.grad.device == tt.device and tt.grad.dtype == t_dtype and tt.grad.shape == tt.shape
+    assert tt.grad.item() == pytest.approx(ref["dt"].sum(), rel=1e-4)
+
+
 @pytest.mark.parametrize("K", [1, 2, 3])
 @pytest.mark.parametrize("ce", [2, -1])
 def test_smallest_degrees_forward_and_backward(gs, clusters, K, ce):

@@ -116,3 +116,26 @@ def test_histogram_gradients_without_grad_t_are_bitwise_equal(gs, swiss, ce):
     for gmu, gnu, _ in outs[1:]:
         assert torch.equal(gmu, outs[0][0]) and torch.equal(gnu, outs[0][1])
     assert np.array_equal(outs[0][2], outs[2][2])
+
+
+def test_growing_checkpoint_interval_on_one_plan(gs, swiss):
+    """A plan first used with checkpoints every 5 iterations (J = 5: one
+    captured segment of length 5), then every 10 with J = 15 (segments of 10
+    and 5): the segment buffers grow, and the second sweep must not replay
+    graphs captured over the old buffers.  Its results are bitwise those of a
+    fresh plan running only the second configuration."""
+    arrs, L = swiss
+    n, K, t, B = 2000, 20, 1.0, 4
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = lam_hat_of(L)
+    rng = np.random.default_rng(123)
+    mu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1))
+    nu = to_dev(np.stack([synth.uniform_on_random_nodes(n, 400, rng) for _ in range(B)], axis=1))
+    reused = gs.Plan(g, K, B)
+    _run(gs, reused, lam, t, mu, nu, 5, 5, None)
+    got = _run(gs, reused, lam, t, mu, nu, 15, 10, None)
+    ref = _run(gs, gs.Plan(g, K, B), lam, t, mu, nu, 15, 10, None)
+    assert np.array_equal(got[0]["dist"], ref[0]["dist"])
+    for i in (1, 2, 3, 4):
+        assert torch.equal(got[i], ref[i]), i
+    assert np.array_equal(got[5], ref[5])

@@ -103,6 +103,55 @@ def test_vertex_weights_equal_rescaled_kernel_problem():
     assert out["D"][0] / (4 * t) == pytest.approx(ref, rel=1e-7)
 
 
+def _dense_plan(L, lam, t, a, v, w):
+    """Explicit plan diag(a v) H diag(a w) with H = exp(-t L_op) from a dense
+    eigendecomposition (no Chebyshev code; at K = 40, t <= 1 the truncation
+    tail is below 1e-40, so p_K equals H to rounding)."""
+    H = heat.heat_dense_exact(L, lam, t)
+    return (a * v)[:, None] * H * (a * w)[None, :]
+
+
+def test_row_marginal_with_vertex_weights_equals_dense_plan_row_sums():
+    """The plan comparator: a v p_K(a w) is the row sum of the explicit plan
+    diag(a v) H diag(a w) (Algorithm 1's plan with vertex weights a; Sec.
+    "Sinkhorn Distances": plan diag(v) K diag(w)), for arbitrary positive
+    scalings v, w (not only at a fixed point) and several columns.  Dropping
+    a from either side, or applying it once, fails."""
+    L, lam = tiny_graph(n=11, k=4, seed=12)
+    t, K = 0.9, 40
+    rng = np.random.default_rng(31)
+    a = rng.uniform(0.3, 2.0, size=11)
+    V = rng.uniform(0.1, 3.0, size=(11, 3))
+    W = rng.uniform(0.1, 3.0, size=(11, 3))
+    got = sinkhorn.row_marginal(L, lam, t, K, V, W, a=a)
+    for c in range(3):
+        ref = _dense_plan(L, lam, t, a, V[:, c], W[:, c]).sum(axis=1)
+        np.testing.assert_allclose(got[:, c], ref, rtol=1e-12, atol=1e-15)
+    # a = None means unit weights
+    ref1 = _dense_plan(L, lam, t, np.ones(11), V[:, 0], W[:, 0]).sum(axis=1)
+    np.testing.assert_allclose(sinkhorn.row_marginal(L, lam, t, K, V[:, 0], W[:, 0])[:, 0], ref1, rtol=1e-12)
+
+
+def test_marginal_errors_with_vertex_weights_equal_dense_plan():
+    """Algorithm 1's reported marginal violations with vertex weights, after a
+    few (unconverged) iterations, equal the L1 distances of the explicit plan's
+    row and column sums to a mu and a nu."""
+    L, lam = tiny_graph(n=10, k=4, seed=13)
+    t, K, J = 0.7, 40, 3
+    rng = np.random.default_rng(32)
+    a = rng.uniform(0.3, 2.0, size=10)
+    mus = np.stack([rand_hist(10, rng, [0, 1, 3, 6, 8]), rand_hist(10, rng)], axis=1)
+    nus = np.stack([rand_hist(10, rng, [2, 4, 5, 7, 9]), rand_hist(10, rng)], axis=1)
+    out = sinkhorn.sinkhorn(L, lam, t, K, mus, nus, J, a=a)
+    for c in range(2):
+        Pi = _dense_plan(L, lam, t, a, out["v"][:, c], out["w"][:, c])
+        row = np.abs(Pi.sum(axis=1) - a * mus[:, c]).sum()
+        col = np.abs(Pi.sum(axis=0) - a * nus[:, c]).sum()
+        assert row > 1e-6                      # unconverged: the pin sees the row side
+        assert out["marg_row"][c] == pytest.approx(row, rel=1e-9)
+        assert out["marg_col"][c] == pytest.approx(col, rel=1e-6, abs=1e-13)
+
+
 def test_columns_are_independent_problems():
     L, lam = tiny_graph(n=10, k=4, seed=8)
     rng = np.random.default_rng(3)
