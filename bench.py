@@ -73,9 +73,17 @@ def parse():
     p.add_argument("--per-cluster", type=int, default=20000, help="points per cluster (50 clusters)")
     p.add_argument("--knn", type=int, default=10)
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--ckpt-figure", type=int, default=10,
+                   help="with records (the default), also time one step with checkpoints every C iterations "
+                        "(0: skip)")
+    p.add_argument("--no-other-graphs", action="store_true",
+                   help="skip the step kernel's roofline on the banded and torus graphs")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the barycenter / plain-forward / Swiss-roll timings")
+    p.add_argument("--study", choices=["orders", "footprint", "frontier"], default=None,
+                   help="instead of the benchmark: the step kernel and its gathers under several node orders, "
+                        "or the gather rate against the operand's footprint")
     p.add_argument("--probe-only", action="store_true",
                    help="set up the workload, then only time the fused step kernel and the copy kernel "
                         "(short run for profilers and counter collection)")
@@ -112,38 +120,71 @@ def measured_traffic(shape_desc: str, n: int, nnz: int, B: int):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(nnz_target: int, n: int, K: int, t: float):
-    """The float64 oracle's forward + reverse sweep on a bounded sample of the workload.
+def cpu_baseline(rp, col, w, K: int, t: float, lam: float, mu, nu, csr_sha: str):
+    """The float64 oracle on a bounded sample of the workload, on its own graph.
 
-    Sample: one Sinkhorn iteration (J = 1) for 2 pairs, K and t as on the GPU,
-    on a synthetic graph of the workload's n and nonzero count with banded
-    locality (building the oracle's own kNN graph at n = 1M by brute force is
-    out of reach on the host).  Applies counted as on the GPU: B * (2J + 2J).
+    The oracle takes the benchmark's exported CSR (float32 weights upcast) and
+    lambda_hat: one heat application at B = 1 and one at B = 16 (scipy CSR
+    products, single thread), and the headline sample, one Sinkhorn iteration
+    forward + reverse sweep (gradients in mu, nu and t) for one pair of the
+    first batch.  Applies counted as on the GPU: B * (2J + 2J); the single
+    applications are reported beside it.
     """
     import numpy as np
 
-    import synth
     from oracle import graph as ograph
+    from oracle import heat
     from oracle import sinkhorn as osk
 
-    k_draw = max(1, int(round(nnz_target / (2.0 * n))))
-    arrs = synth.random_local_graph(n, k_draw, 20000, np.random.default_rng(91))
-    L = ograph.laplacian(ograph.csr_from_arrays(n, *arrs))
-    lam = float(np.max(np.asarray(L.diagonal())) * 2.0)
-    B, J = 2, 1
-    mu = np.stack([synth.histogram_on_random_support(n, 20000, 1.0, 93 + b) for b in range(B)], axis=1)
-    nu = np.stack([synth.histogram_on_random_support(n, 20000, 1.0, 97 + b) for b in range(B)], axis=1)
+    n = rp.shape[0] - 1
+    L = ograph.laplacian(ograph.csr_from_arrays(n, rp, col, w.astype(np.float64)))
+    rng = np.random.default_rng(12)
+    single = {}
+    for B in (1, 16):
+        x = rng.uniform(0.05, 1.0, size=(n, B))
+        t0 = time.perf_counter()
+        heat.heat_apply(L, lam, t, K, x)
+        dt = time.perf_counter() - t0
+        single[f"B={B}"] = {"seconds": round(dt, 2), "applies_per_s": round(B / dt, 3)}
+    J = 1
     t0 = time.perf_counter()
-    osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J)
+    osk.sinkhorn_grad(L, lam, t, K, mu[:, :1].astype(np.float64), nu[:, :1].astype(np.float64), J)
     dt = time.perf_counter() - t0
-    applies = B * (2 * J + 2 * J)
+    applies = 1 * (2 * J + 2 * J)
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": applies / dt, "unit": "heat-kernel applies/s", "cores": 1, "kind": "oracle",
             "sample": (f"float64 oracle (scipy CSR products, single thread; host affinity {ncores} cores, "
-                       f"os.cpu_count() {os.cpu_count()}): "
-                       f"1 Sinkhorn iteration forward + reverse sweep for {B} pairs, K={K}, t={t}, on a "
-                       f"synthetic banded graph with n={n}, nnz={int(arrs[1].shape[0])} (workload nnz "
-                       f"{nnz_target}); {applies} applies in {dt:.1f} s")}
+                       f"os.cpu_count() {os.cpu_count()}) on the workload's own graph (exported CSR sha256 "
+                       f"{csr_sha[:16]}, n={n}, nnz={col.shape[0]}, same lambda_hat): 1 Sinkhorn iteration "
+                       f"forward + reverse sweep for 1 pair of the first batch, K={K}, t={t}; {applies} applies "
+                       f"in {dt:.1f} s"),
+            "single_applies": single}
+
+
+def roofline_on_other_graphs(gs, synth, np, torch, dev, K: int, B: int):
+    """The step kernel on 1M-node graphs whose gathers can hit cache, in its autotuned launch.
+
+    band_matched_nnz: each node draws 9 partners within +-20,000 ids (18.0M
+    nonzeros, the kNN graph's size); band_narrow: within +-2,000 ids; torus:
+    the 1000 x 1000 torus (4 nonzeros per row).  Same algorithmic byte count
+    and peak as the headline roofline.
+    """
+    out = {}
+    graphs = {"band_matched_nnz": lambda: synth.random_local_graph(1_000_000, 9, 20000, np.random.default_rng(91)),
+              "band_narrow": lambda: synth.random_local_graph(1_000_000, 9, 2000, np.random.default_rng(92)),
+              "torus_1000x1000": lambda: synth.torus_graph(1000, 1000)}
+    for name, make in graphs.items():
+        arrs = make()
+        n = arrs[0].shape[0] - 1
+        g = gs.gs_graph_from_csr(n, *arrs)
+        plan = gs.Plan(g, K, B, flags=gs.GS_PLAN_AUTOTUNE)
+        ms, _ = gs.gs_plan_time_step(plan, reps=4)
+        alg = method_step_bytes(n, g.nnz, B, K)
+        out[name] = {"n": n, "nnz": g.nnz, "us": round(ms * 1e3, 1), "achieved_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "plan": plan.describe()}
+        log(f"[roofline] {name}: {ms * 1e3:.1f} us, frac {out[name]['frac']:.3f}")
+        del plan, g
+    return out
 
 
 def extra_workloads(gs, synth, np, torch, dev):
@@ -315,6 +356,227 @@ def extra_workloads(gs, synth, np, torch, dev):
     return out
 
 
+def node_orders(X, labels, rp, col, np):
+    """Node orders of the 1M workload compared by the order study (new id -> old id).
+
+    generator: cluster after cluster (the generator's own order); random: a
+    uniform permutation; cluster_grid: the clusters of the 10 x 5 parameter grid
+    renumbered column-major, so grid neighbours (the clusters a node's kNN
+    edges mostly reach) are adjacent; rcm: reverse Cuthill-McKee of the graph;
+    pca: sorted by the first principal component; pca_bisect: recursive
+    bisection at the median of each part's own first principal component down
+    to parts of <= 4096 nodes (a geometric partition order).
+    """
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+
+    n = X.shape[0]
+    out = {"generator": np.arange(n), "random": np.random.default_rng(7).permutation(n)}
+    grid = np.arange(50).reshape(10, 5)
+    cl_order = grid.T.ravel()                      # column-major walk of the 10 x 5 grid
+    out["cluster_grid"] = np.concatenate([np.nonzero(labels == c)[0] for c in cl_order])
+    A = csr_matrix((np.ones(col.shape[0], dtype=np.float32), col, rp), shape=(n, n))
+    out["rcm"] = np.asarray(reverse_cuthill_mckee(A, symmetric_mode=True), dtype=np.int64)
+
+    def top_pc(Y):
+        Yc = Y - Y.mean(axis=0)
+        v = np.random.default_rng(0).standard_normal(Y.shape[1])
+        for _ in range(8):
+            v = Yc.T @ (Yc @ v)
+            v /= np.linalg.norm(v)
+        return Yc @ v
+
+    out["pca"] = np.argsort(top_pc(X), kind="stable")
+    parts = [np.arange(n)]
+    while max(len(p) for p in parts) > 4096:
+        nxt = []
+        for p in parts:
+            if len(p) <= 4096:
+                nxt.append(p)
+                continue
+            o = np.argsort(top_pc(X[p]), kind="stable")
+            h = len(p) // 2
+            nxt += [p[o[:h]], p[o[h:]]]
+        parts = nxt
+    out["pca_bisect"] = np.concatenate(parts)
+    return out
+
+
+def permuted_csr(rp, col, w, order, np):
+    """CSR of the graph renumbered so that new node i is old node order[i] (rows sorted by column)."""
+    n = rp.shape[0] - 1
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n)
+    deg = np.diff(rp)[order]
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum(deg)
+    src = np.repeat(np.arange(n), deg)
+    starts = rp[order]
+    e_old = starts[src] + (np.arange(rp2[-1]) - rp2[src])
+    c2 = inv[col[e_old]]
+    w2 = w[e_old]
+    key = src * n + c2
+    o = np.argsort(key, kind="stable")
+    return rp2.astype(np.int32), c2[o].astype(np.int32), w2[o].astype(np.float32)
+
+
+def order_study(args):
+    """The step kernel and its gathers alone under each node order of the 1M workload (one JSON line)."""
+    import numpy as np
+    import torch
+
+    import paper_2211_00805_amd as gs
+    import synth
+
+    dev = torch.device("cuda:0")
+    X, labels = synth.clusters_on_surface((10, 5), args.per_cluster, 100, 0.1, workload=5)
+    g0 = gs.gs_graph_from_points(X, args.knn)
+    rp, col, w, _ = g0.export()
+    del g0
+    log("[study] computing node orders ...")
+    orders = node_orders(X, labels, rp, col, np)
+    del X
+    K, B = args.K, 32
+    res = {"study": "node orders", "n": int(rp.shape[0] - 1), "nnz": int(col.shape[0]), "K": K, "B": B,
+           "shape": "vec=4 S=2 C=8 xcd=1", "orders": {}}
+    for name, order in orders.items():
+        rp2, c2, w2 = permuted_csr(rp, col, w, order, np)
+        n = rp2.shape[0] - 1
+        rows = np.repeat(np.arange(n), np.diff(rp2))
+        d = np.abs(rows - c2.astype(np.int64))
+        g = gs.gs_graph_from_csr(n, rp2, c2, w2)
+        plan = gs.Plan(g, K, B)
+        plan.set_shape(4, 2, 8)
+        step_ms, _ = gs.gs_plan_time_step(plan, reps=4)
+        idx = torch.from_numpy(c2).to(dev)
+        Xop = torch.ones((n, 32), device=dev)
+        gout = torch.empty((len(c2) + 31) // 32 * 32, device=dev)
+        for _ in range(2):
+            gs.gs_stream_gather(Xop, idx, gout)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            gs.gs_stream_gather(Xop, idx, gout)
+        e1.record()
+        torch.cuda.synchronize()
+        gather_us = e0.elapsed_time(e1) * 1e3 / 5
+        alg = method_step_bytes(n, len(c2), B, K)
+        res["orders"][name] = {"step_us": round(step_ms * 1e3, 1), "gather_us": round(gather_us, 1),
+                               "frac": round(alg / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                               "median_abs_i_minus_j": float(np.median(d)),
+                               "within_16k": round(float(np.mean(d < 16384)), 4),
+                               "within_128k": round(float(np.mean(d < 131072)), 4)}
+        log(f"[study] {name}: {res['orders'][name]}")
+        del plan, g, idx, Xop, gout
+    print(json.dumps(res), flush=True)
+
+
+def footprint_study(args):
+    """Gather rate against the gathered operand's footprint (one JSON line).
+
+    The step kernel's gather path alone (gs_stream_gather: one 128-byte row of
+    an rows x 32 float32 operand per index, 18,322,390 indices as the 1M kNN
+    graph has nonzeros): uniform random indices over operands from 1 MB
+    (inside one XCD's 4 MB L2) through 128 MB (the 1M operand; inside the
+    256 MB Infinity Cache) to 2 GB (HBM only); and indices within +-W rows of a
+    ramp over a 1M-row operand (banded locality).
+    """
+    import torch
+
+    import paper_2211_00805_amd as gs
+
+    dev = torch.device("cuda:0")
+    m = 18322390
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    out = torch.empty((m + 31) // 32 * 32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def gather_us(Xop, idx, reps=5):
+        gs.gs_stream_gather(Xop, idx, out)
+        e0.record()
+        for _ in range(reps):
+            gs.gs_stream_gather(Xop, idx, out)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    res = {"study": "gather footprint", "indices": m, "row_bytes": 128, "uniform": {}, "band_1M_rows": {}}
+    for rows in [8192, 16384, 32768, 65536, 131072, 262144, 524288, 1 << 20, 2 << 20, 4 << 20, 8 << 20, 16 << 20]:
+        Xop = torch.ones((rows, 32), device=dev)
+        idx = torch.randint(0, rows, (m,), device=dev, dtype=torch.int32, generator=gen)
+        us = gather_us(Xop, idx)
+        res["uniform"][str(rows)] = {"MB": round(rows * 128 / 1e6, 1), "us": round(us, 1),
+                                     "gbs": round(m * 128 / us / 1e3, 1)}
+        log(f"[study] uniform over {rows} rows: {res['uniform'][str(rows)]}")
+        del Xop, idx
+    n = 1 << 20
+    Xop = torch.ones((n, 32), device=dev)
+    ramp = torch.arange(m, device=dev, dtype=torch.int64) * n // m
+    for W in [512, 2048, 8192, 32768, 131072, 524288]:
+        off = torch.randint(-W, W + 1, (m,), device=dev, generator=gen)
+        idx = ((ramp + off) % n).to(torch.int32)
+        us = gather_us(Xop, idx)
+        res["band_1M_rows"][str(W)] = {"us": round(us, 1), "gbs": round(m * 128 / us / 1e3, 1)}
+        log(f"[study] band +-{W}: {res['band_1M_rows'][str(W)]}")
+    print(json.dumps(res), flush=True)
+
+
+def frontier_study(args):
+    """Work a frontier-sparse step could skip, per workload (one JSON line).
+
+    T_k of an application is zero outside the k-hop neighbourhood N^k(S) of the
+    applied vector's support S (the union over the B columns of a launch, since
+    a row is skipped only when all its columns are zero), so step k could skip
+    the rows outside N^k(S), at most.  Reported: the fraction of rows and of
+    nonzeros (the gathers) inside N^k(S) for k = 0..4, and the largest share
+    of an application's gathers a frontier-sparse kernel could skip,
+    sum_k (1 - nnz(N^{k-1}(S)) / nnz) / K (step k gathers T_{k-1}).
+    """
+    import numpy as np
+    import scipy.sparse as sp
+
+    import paper_2211_00805_amd as gs
+    import synth
+
+    def reach(rp, col, S, K):
+        n = rp.shape[0] - 1
+        A = sp.csr_matrix((np.ones(col.shape[0], dtype=np.float32), col, rp), shape=(n, n))
+        deg = np.diff(rp).astype(np.float64)
+        f = S.copy()
+        rows, nnzs = [], []
+        for k in range(K):
+            rows.append(float(f.mean()))
+            nnzs.append(float(deg[f].sum() / deg.sum()))
+            if k < K - 1:
+                f = f | (A @ f.astype(np.float32) > 0)
+        skip = float(np.sum(1.0 - np.asarray(nnzs)) / K)   # step k gathers T_{k-1}: hops 0..K-1
+        return {"rows_reached": [round(x, 4) for x in rows[:5]], "nnz_reached": [round(x, 4) for x in nnzs[:5]],
+                "max_skippable_gather_share": round(skip, 4)}
+
+    res = {"study": "frontier", "workloads": {}}
+    X, labels, mu, nu = synth.curve_pair_workload()
+    g = gs.gs_graph_from_points(X, 15)
+    rp, col, _, _ = g.export()
+    res["workloads"]["100k curve, one pair (mu on clusters 0-3), K = 30"] = reach(rp, col, mu > 0, 30)
+    X, labels, _ = synth.barycenter_workload()
+    g = gs.gs_graph_from_points(X, 15)
+    rp, col, _, _ = g.export()
+    gm, gn = synth.gradient_pairs(labels)
+    res["workloads"]["200k gradients, 32 pairs (union of the mu supports), K = 30"] = reach(rp, col, (gm > 0).any(axis=1), 30)
+    res["workloads"]["200k gradients, pair 0 alone, K = 30"] = reach(rp, col, gm[:, 0] > 0, 30)
+    X, labels = synth.clusters_on_surface((10, 5), args.per_cluster, 100, 0.1, workload=5)
+    g = gs.gs_graph_from_points(X, args.knn)
+    rp, col, _, _ = g.export()
+    n = rp.shape[0] - 1
+    sizes = synth.loguniform_support_sizes(n, 256, 5000, 200000, synth.seed_for(5, 2))
+    S = np.zeros(n, dtype=bool)
+    for i in range(32):
+        S |= synth.histogram_on_random_support(n, int(sizes[i]), 1.0, synth.seed_for(5, 2) * 1000 + i) > 0
+    res["workloads"]["1M kNN, a batch of 32 random supports, K = 50"] = reach(rp, col, S, 50)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -322,6 +584,16 @@ def main():
               "the method would shard by pairs (each GPU a share of the pair batches on a full graph replica, "
               "one all-reduce of the histogram gradients at the end).", file=sys.stderr)
         sys.exit(2)
+
+    if args.study == "orders":
+        order_study(args)
+        return
+    if args.study == "footprint":
+        footprint_study(args)
+        return
+    if args.study == "frontier":
+        frontier_study(args)
+        return
 
     import numpy as np
     import torch
@@ -385,6 +657,9 @@ def main():
     log(f"[setup] plan: {shape}")
     if args.probe_only:
         step_ms, step_bytes = gs.gs_plan_time_step(plan, reps=2)
+        plan.set_kernel(gs.GS_KERNEL_CLENSHAW)
+        clen_ms, _ = gs.gs_plan_time_step(plan, reps=2)
+        plan.set_kernel(gs.GS_KERNEL_CHEBYSHEV)
         nb = 1 << 30
         src = torch.ones(nb // 4, device=dev)
         dst = torch.empty_like(src)
@@ -405,8 +680,9 @@ def main():
             torch.cuda.synchronize()
             gather_us = ev0.elapsed_time(ev1) * 1e3 / 3
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "2 applications (K step launches each) + copy of 1 GiB x3 + 3 gather passes",
-                          "step_ms": step_ms, "gather_us": gather_us,
+        print(json.dumps({"probe": "2 applications (K step launches each), 2 in Clenshaw's form + copy of 1 GiB x3 "
+                                   "+ 3 gather passes",
+                          "step_ms": step_ms, "clenshaw_step_ms": clen_ms, "gather_us": gather_us,
                           "step_kernel_bytes": step_bytes, "step_algorithmic_bytes": method_step_bytes(n, g.nnz, P, K),
                           "copy_bytes_read": nb, "copy_bytes_written": nb,
                           "plan": shape, "shape": shape_key(shape), "kernel_sha": kernel_source_hash(),
@@ -458,11 +734,40 @@ def main():
     value = applies_per_step / (ms_per_step / 1e3)
     finite = all(np.all(np.isfinite(d)) for d in dists) and bool(torch.isfinite(G).all())
 
+    # ---------------------------------------------------------------- checkpointed form (one step)
+    ckpt_fig = None
+    if ce == gs.GS_RECORD_ALL and args.ckpt_figure > 0:
+        C = args.ckpt_figure
+        ck = torch.empty(gs.ckpt_floats(plan, J, C), device=dev)
+
+        def step_ck(ci, cj):
+            gs.gs_gather_columns(Hdev, ci, mu)
+            gs.gs_gather_columns(Hdev, cj, nu)
+            gs.gs_sinkhorn(plan, lam, t, mu, nu, J, ckpt_every=C, ckpt=ck)
+            gs.gs_sinkhorn_backward(plan, lam, t, mu, nu, J, C, ck, ones, grad_mu=gmu, grad_nu=gnu)
+
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        step_ck(*dev_batches[args.warmup])
+        torch.cuda.synchronize()
+        tck = time.perf_counter() - w0
+        seg_gb = 2 * C * n * P * 4 / 1e9
+        ckpt_fig = {"ckpt_every": C, "ms_per_step": round(tck * 1e3, 1),
+                    "value": round(applies_per_step / tck, 1), "unit": "heat-kernel applies/s",
+                    "recompute_applies_per_step": P * 2 * J,
+                    "hbm_gb": {"checkpoints": round(ck.numel() * 4 / 1e9, 2), "segment_slots": round(seg_gb, 2),
+                               "records_instead": round(ckpt.numel() * 4 / 1e9, 2)}}
+        log(f"[ckpt] checkpoints every {C}: {tck:.2f}s per step -> {applies_per_step / tck:.0f} applies/s")
+        del ck
+
     # ---------------------------------------------------------------- fused step roofline (HIP events)
     # achieved = the method's bytes per step launch / the launch's HIP-event time; the fused
     # kernel itself moves fewer (it touches the accumulator only on every third step):
     # reported beside it as kernel_bytes_per_launch
     step_ms, kernel_bytes = gs.gs_plan_time_step(plan, reps=10)
+    plan.set_kernel(gs.GS_KERNEL_CLENSHAW)   # the same polynomial by Clenshaw's recurrence, same launch shape
+    clen_ms, clen_bytes = gs.gs_plan_time_step(plan, reps=10)
+    plan.set_kernel(gs.GS_KERNEL_CHEBYSHEV)
     alg_bytes = method_step_bytes(n, g.nnz, P, K)
     achieved = alg_bytes / (step_ms * 1e-3) / 1e9
     traffic = measured_traffic(shape, n, g.nnz, P)
@@ -473,7 +778,9 @@ def main():
                 "algorithmic_bytes_rule": "per step 4(n+1) + 8 nnz + 4n (CSR, degrees) + 20nB (T_{k-1} gathered once, "
                                           "T_{k-2}, T_k, accumulator read + write), 12nB at k = 1; averaged over K",
                 "kernel_bytes_per_launch": int(kernel_bytes),
-                "kernel_gbs": round(kernel_bytes / (step_ms * 1e-3) / 1e9, 1)}
+                "kernel_gbs": round(kernel_bytes / (step_ms * 1e-3) / 1e9, 1),
+                "clenshaw_form": {"avg_ms": round(clen_ms, 5), "kernel_bytes_per_launch": int(clen_bytes),
+                                  "over_accumulating_form": round(clen_ms / step_ms, 4)}}
     log(f"[roofline] step {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({achieved / PEAK_HBM_GBS:.1%}); "
         f"kernel's own bytes {roofline['kernel_gbs']:.0f} GB/s")
 
@@ -562,8 +869,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[cpu] timing the oracle ...")
-        cpu = cpu_baseline(g.nnz, n, K, t)
+        gs.gs_gather_columns(Hdev, dev_batches[0][0], mu)
+        gs.gs_gather_columns(Hdev, dev_batches[0][1], nu)
+        rp_, col_, w_, _ = g.export()
+        cpu = cpu_baseline(rp_, col_, w_, K, t, lam, mu[:, :1].cpu().numpy(), nu[:, :1].cpu().numpy(),
+                           inputs["csr_sha256"])
+        del rp_, col_, w_
         log(f"[cpu] {cpu['value']:.3f} applies/s")
+
+    other_graphs = None
+    if not args.no_other_graphs:
+        del ckpt
+        other_graphs = roofline_on_other_graphs(gs, synth, np, torch, dev, K, P)
+        roofline["same_kernel_other_graphs"] = other_graphs
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "heat-kernel applies/s", "n_gpus": 1,
@@ -584,6 +902,7 @@ def main():
         "cpu_baseline": cpu,
         "sinkhorn_iters_per_s": round(P * J / (ms_per_step / 1e3), 1),
         "recompute_applies_per_step": 0 if ce == gs.GS_RECORD_ALL else P * 2 * J,
+        "checkpointed_form": ckpt_fig,
         "step_kernel_gbs_algorithmic": round(achieved, 1),
         "copy_kernel_gbs": round(copy_gbs, 1),
         "gather_reference": gather_ref,

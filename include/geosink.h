@@ -121,10 +121,12 @@ void gs_graph_destroy(gs_graph g);
 
 /* Estimate lambda_hat >= lambda_max(L) for the rescaling L_op = (2/lambda_hat) L.
  * Runs `iters` (>= 2) Lanczos steps on the GPU from a start vector drawn with
- * `seed`, takes the largest Ritz value theta and returns
- * min(safety * theta, edge_bound); safety >= 1.  The paper only assumes the
- * spectrum is bounded; the bound check keeps the result valid when the
- * safety factor is too generous.  Synchronises `stream`. */
+ * `seed`, takes the largest Ritz value theta with its residual norm
+ * r = ||L y - theta y|| (= beta_m |s_m|: L has an eigenvalue within r of theta)
+ * and returns min(max(safety * theta, theta + r), edge_bound); safety >= 1.
+ * The paper only assumes the spectrum is bounded; the residual covers a Ritz
+ * value that has not converged to within the safety factor, and the edge bound
+ * max_E(d_i + d_j) >= lambda_max caps a generous factor.  Synchronises `stream`. */
 gs_status gs_lambda_max(gs_graph g, int32_t iters, uint64_t seed, double safety,
                         hipStream_t stream, double* lambda_hat);
 
@@ -165,6 +167,7 @@ gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C);
 /* Kernel a plan applies in gs_heat_apply, gs_sinkhorn and gs_barycenter. */
 #define GS_KERNEL_CHEBYSHEV 0 /* p_K(L, t): degree-K Chebyshev sum (default) */
 #define GS_KERNEL_EULER 1     /* backward-Euler (I + (t/N) L_op)^{-N}       */
+#define GS_KERNEL_CLENSHAW 2  /* the same p_K(L, t) by Clenshaw's recurrence */
 
 /* Select the heat-kernel approximation (paper, Sec. "Related work": the heat
  * kernel applied by solving the linear systems of an implicit discretisation

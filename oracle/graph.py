@@ -17,29 +17,35 @@ from scipy.sparse.csgraph import connected_components
 from scipy.spatial.distance import cdist
 
 
-def knn_lists(X: np.ndarray, k: int, block: int = 512):
+def knn_lists(X: np.ndarray, k: int, block: int = 512, rows: tuple[int, int] | None = None):
     """k nearest other points of every point, by Euclidean distance.
 
     Brute force over row blocks with direct squared differences (cdist).
     Order within a row is by (distance, node id); equal distances go to the
-    lower id.  Returns (idx int64 (n, k), d2 float64 (n, k)).
+    lower id.  Returns (idx int64 (n, k), d2 float64 (n, k)); with
+    rows = (lo, hi) only the points lo..hi-1 are searched (against all n
+    points) and the arrays have hi - lo rows, so a large cloud can be split
+    over processes.
     """
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     if not 1 <= k < n:
         raise ValueError("need 1 <= k < n")
-    idx = np.empty((n, k), dtype=np.int64)
-    d2 = np.empty((n, k), dtype=np.float64)
-    for r0 in range(0, n, block):
-        r1 = min(n, r0 + block)
+    lo, hi = (0, n) if rows is None else (int(rows[0]), int(rows[1]))
+    if not 0 <= lo <= hi <= n:
+        raise ValueError("rows out of range")
+    idx = np.empty((hi - lo, k), dtype=np.int64)
+    d2 = np.empty((hi - lo, k), dtype=np.float64)
+    for r0 in range(lo, hi, block):
+        r1 = min(hi, r0 + block)
         D = cdist(X[r0:r1], X, metric="sqeuclidean")
         D[np.arange(r1 - r0), np.arange(r0, r1)] = np.inf  # no self edge
         thresh = np.partition(D, k - 1, axis=1)[:, k - 1]
         for r in range(r1 - r0):
             cand = np.nonzero(D[r] <= thresh[r])[0]          # ascending ids
             order = np.lexsort((cand, D[r, cand]))[:k]       # by distance, then id
-            idx[r0 + r] = cand[order]
-            d2[r0 + r] = D[r, cand[order]]
+            idx[r0 - lo + r] = cand[order]
+            d2[r0 - lo + r] = D[r, cand[order]]
     return idx, d2
 
 
@@ -50,16 +56,24 @@ def pair_sqdist(X: np.ndarray, i: np.ndarray, j: np.ndarray) -> np.ndarray:
     return np.einsum("ed,ed->e", diff, diff)
 
 
-def knn_graph(X: np.ndarray, k: int):
+def gaussian_weights(X: np.ndarray, i: np.ndarray, j: np.ndarray, m: float) -> np.ndarray:
+    """Affinity exp(-||x_i - x_j||^2 / m^2) of the point pairs (i, j)."""
+    return np.exp(-pair_sqdist(X, i, j) / (m * m))
+
+
+def knn_graph(X: np.ndarray, k: int, knn_idx: np.ndarray | None = None):
     """Symmetrised kNN graph with Gaussian-median weights.
 
     Returns (A, info): A is a float64 scipy CSR adjacency with sorted column
     ids and no self loops; info holds the directed kNN lists, the median
-    distance m and the component count.
+    distance m and the component count.  knn_idx, when given, is the (n, k)
+    result of knn_lists (e.g. assembled from row ranges searched apart).
     """
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
-    idx, _ = knn_lists(X, k)
+    idx = knn_lists(X, k)[0] if knn_idx is None else np.asarray(knn_idx, dtype=np.int64)
+    if idx.shape != (n, k):
+        raise ValueError("knn_idx must be (n, k)")
     src = np.repeat(np.arange(n, dtype=np.int64), k)
     dst = idx.ravel()
     d_dir = np.sqrt(pair_sqdist(X, src, dst))               # directed kNN distances
@@ -68,7 +82,7 @@ def knn_graph(X: np.ndarray, k: int):
     hi = np.maximum(src, dst)
     key = np.unique(lo * n + hi)                           # union of the directed edges
     a, b = key // n, key % n
-    w = np.exp(-pair_sqdist(X, a, b) / (m * m))
+    w = gaussian_weights(X, a, b, m)
     A = sp.coo_matrix((np.concatenate([w, w]), (np.concatenate([a, b]), np.concatenate([b, a]))),
                       shape=(n, n)).tocsr()
     A.sort_indices()

@@ -40,6 +40,7 @@ GS_PLAN_AUTOTUNE = 1
 GS_PLAN_NO_GRAPH = 2
 GS_KERNEL_CHEBYSHEV = 0
 GS_KERNEL_EULER = 1
+GS_KERNEL_CLENSHAW = 2
 GS_RECORD_ALL = -1
 GS_MAX_K = 256
 

@@ -14,11 +14,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (GS_KERNEL_CHEBYSHEV, GS_KERNEL_EULER, GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GS_RECORD_ALL,
+from ._lib import (GS_KERNEL_CHEBYSHEV, GS_KERNEL_CLENSHAW, GS_KERNEL_EULER, GS_PLAN_AUTOTUNE, GS_PLAN_NO_GRAPH, GS_RECORD_ALL,
                    GeoSinkError, check, lib)
 
 __all__ = [
-    "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "GS_KERNEL_CHEBYSHEV", "GS_KERNEL_EULER",
+    "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "GS_KERNEL_CHEBYSHEV", "GS_KERNEL_CLENSHAW", "GS_KERNEL_EULER",
     "GS_RECORD_ALL", "ckpt_floats",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
     "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",

@@ -200,7 +200,8 @@ gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
 gs_status gs_plan_set_kernel(gs_plan p, int32_t kernel, int32_t N, int32_t cg_iters) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr, "plan is NULL");
-        GS_REQUIRE(kernel == GS_KERNEL_CHEBYSHEV || kernel == GS_KERNEL_EULER, "unknown kernel");
+        GS_REQUIRE(kernel == GS_KERNEL_CHEBYSHEV || kernel == GS_KERNEL_CLENSHAW || kernel == GS_KERNEL_EULER,
+                   "unknown kernel");
         if (kernel == GS_KERNEL_EULER) {
             GS_REQUIRE(N >= 1 && N <= 1024, "N must be in [1, 1024]");
             GS_REQUIRE(cg_iters >= 0 && cg_iters <= 1000, "cg_iters must be in [0, 1000]");
@@ -220,7 +221,8 @@ gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len) {
                               (p->kernel == GS_KERNEL_EULER
                                    ? " kernel=euler N=" + std::to_string(p->euler_N) + " cg=" +
                                          (p->cg_iters > 0 ? std::to_string(p->cg_iters) : std::string("auto"))
-                                   : std::string(" kernel=chebyshev"));
+                                   : std::string(p->kernel == GS_KERNEL_CLENSHAW ? " kernel=clenshaw"
+                                                                                 : " kernel=chebyshev"));
         std::strncpy(buf, s.c_str(), len - 1);
         buf[len - 1] = 0;
     });
@@ -234,8 +236,8 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
         check_plan_args(p, lambda_hat, t);
         GS_REQUIRE(X != nullptr && Y != nullptr, "X / Y is NULL");
         GS_REQUIRE(X != Y && (const float*)Ydt != X && Ydt != Y, "X, Y and Ydt must be distinct");
-        GS_REQUIRE(Ydt == nullptr || p->kernel == GS_KERNEL_CHEBYSHEV,
-                   "the time derivative needs the Chebyshev kernel");
+        GS_REQUIRE(Ydt == nullptr || p->kernel != GS_KERNEL_EULER,
+                   "the time derivative needs a Chebyshev kernel");
         heat_apply(*p, lambda_hat, t, X, Y, Ydt, stream);
     });
 }
@@ -261,7 +263,7 @@ gs_status gs_sinkhorn_backward(gs_plan p, double lambda_hat, double t, const flo
                                hipStream_t stream) {
     return guarded([&] {
         check_plan_args(p, lambda_hat, t);
-        GS_REQUIRE(p->kernel == GS_KERNEL_CHEBYSHEV, "the reverse sweep needs the Chebyshev kernel");
+        GS_REQUIRE(p->kernel != GS_KERNEL_EULER, "the reverse sweep needs a Chebyshev kernel");
         GS_REQUIRE(t > 0.0, "t must be > 0 for the backward");
         GS_REQUIRE(mu != nullptr && nu != nullptr && ckpt != nullptr && grad_dist != nullptr,
                    "mu / nu / ckpt / grad_dist is NULL");

@@ -74,7 +74,9 @@ enum StepFlags : int32_t {
     STEP_DUAL = 4,       // second accumulator with the d/dt coefficients
     STEP_ACC_WRITE = 8,  // store the accumulator(s)
     STEP_EPI_SCALE = 16, // last step: out = num / floor(acc); out_a = a * out; record floors
-    STEP_ACC_READ = 32   // accumulator(s) hold earlier terms (else they start at 0)
+    STEP_ACC_READ = 32,  // accumulator(s) hold earlier terms (else they start at 0)
+    STEP_CLENSHAW = 64,  // Clenshaw form: out = c_y (y G) - u_{k+2} + c_x X, G gathered (tprev)
+    STEP_CLEN_P2 = 128   // Clenshaw step reads u_{k+2} from tprev2 (products 3..K)
 };
 
 struct StepArgs {
@@ -105,6 +107,7 @@ struct StepArgs {
     float* rec;
     float phi;
     unsigned long long* nfloor;
+    const float* xin;     // Clenshaw: the applied signal X (read on every product)
 };
 
 struct LaunchShape {

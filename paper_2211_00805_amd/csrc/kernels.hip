@@ -117,8 +117,9 @@ __device__ __forceinline__ void vacc(Vec<VEC>& sum, float w, const Vec<VEC>& own
 // step and the last), each adding up to three terms b_{k-2} T_{k-2},
 // b_{k-1} T_{k-1}, b_k T_k that the step already holds.
 //
-// DUAL selects the adjoint form with a second accumulator (its own symbol, so
-// profiles separate forward steps from adjoint steps).
+// MODE selects the accumulating form, the adjoint form with a second
+// accumulator, or Clenshaw's recurrence (each its own symbol, so profiles
+// separate them).
 constexpr int kChunk = 2048;   // staged (col, weight) pairs per block and pass
 // Gathers in flight per lane: 5 is the deepest unroll whose registers fit in
 // 64 VGPRs, i.e. 8 waves per SIMD; measured on the 1M-node graph at B = 32,
@@ -127,9 +128,22 @@ constexpr int kUnroll = 5;
 
 __device__ __forceinline__ float coef_at(const float* b, int idx) { return idx == 0 ? 0.5f * b[0] : b[idx]; }
 
+// Step forms: the accumulating recurrence, its adjoint form with a second
+// accumulator, and Clenshaw's backward recurrence (no accumulator).
+constexpr int kModeFwd = 0, kModeDual = 1, kModeClen = 2;
+
 // Step epilogue for one row and one group of VEC columns: the three-term
 // update, the accumulator flush and (last step) Algorithm 1's scaling.
-template <int VEC, bool DUAL>
+//
+// Clenshaw form (MODE == kModeClen), product j = A.k of K for
+// p_K X = b_0/2 X + sum_k b_k T_k(y) X: with u_{K+1} = u_{K+2} = 0,
+// u_k = 2 y u_{k+1} - u_{k+2} + b_k X (k = K-1..1) and the result
+// y u_1 - u_2 + (b_0/2) X.  Product j gathers G = u_{K-j+1} (X standing
+// for u_K = b_K X when j = 1) and writes u_{K-j}, or the result when j = K:
+//   out = c_y (y G) - [u_{K-j+2}, read when j >= 3] + c_x X,
+//   c_y = (j < K ? 2 : 1) * (j == 1 ? b_K : 1),  c_x = b_{K-j} (b_0 halved)
+//   minus b_K when j == 2 (u_K = b_K X folded in).
+template <int VEC, int MODE>
 __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t off, const Vec<VEC>& own,
                                               const Vec<VEC>& p2, const Vec<VEC>& ac, const Vec<VEC>& ac2,
                                               const Vec<VEC>& sx, float sw) {
@@ -137,25 +151,37 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t
     const int k = A.k;
     const float alpha = A.coef[0];
     const float* b = A.coef + 1;
-    const float* db = A.coef + 2 + A.K;
-    const int m = A.cmask;
-    const float c2 = (m & 1) ? coef_at(b, k - 2) : 0.f;
-    const float c1 = (m & 2) ? coef_at(b, k - 1) : 0.f;
-    const float c0 = (m & 4) ? coef_at(b, k) : 0.f;
     Vec<VEC> t, accn, acc2n;
+    if constexpr (MODE == kModeClen) {
+        const int K = A.K;
+        const float cy = (k < K ? 2.f : 1.f) * (k == 1 ? b[K] : 1.f);
+        const float cx = coef_at(b, K - k) - (k == 2 ? b[K] : 0.f);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y T_{k-1})_i
-        t.v[i] = (flags & STEP_FIRST) ? yx : fmaf(2.f, yx, -p2.v[i]);
-        accn.v[i] = fmaf(c0, t.v[i], fmaf(c1, own.v[i], fmaf(c2, p2.v[i], ac.v[i])));
-    }
-    if constexpr (DUAL) {
-        const float d2 = (m & 1) ? coef_at(db, k - 2) : 0.f;
-        const float d1 = (m & 2) ? coef_at(db, k - 1) : 0.f;
-        const float d0 = (m & 4) ? coef_at(db, k) : 0.f;
+        for (int i = 0; i < VEC; ++i) {
+            const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y G)_i
+            t.v[i] = fmaf(cy, yx, fmaf(cx, ac.v[i], -p2.v[i]));                       // ac holds X
+            accn.v[i] = t.v[i];
+        }
+    } else {
+        const float* db = A.coef + 2 + A.K;
+        const int m = A.cmask;
+        const float c2 = (m & 1) ? coef_at(b, k - 2) : 0.f;
+        const float c1 = (m & 2) ? coef_at(b, k - 1) : 0.f;
+        const float c0 = (m & 4) ? coef_at(b, k) : 0.f;
 #pragma unroll
-        for (int i = 0; i < VEC; ++i)
-            acc2n.v[i] = fmaf(d0, t.v[i], fmaf(d1, own.v[i], fmaf(d2, p2.v[i], ac2.v[i])));
+        for (int i = 0; i < VEC; ++i) {
+            const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y T_{k-1})_i
+            t.v[i] = (flags & STEP_FIRST) ? yx : fmaf(2.f, yx, -p2.v[i]);
+            accn.v[i] = fmaf(c0, t.v[i], fmaf(c1, own.v[i], fmaf(c2, p2.v[i], ac.v[i])));
+        }
+        if constexpr (MODE == kModeDual) {
+            const float d2 = (m & 1) ? coef_at(db, k - 2) : 0.f;
+            const float d1 = (m & 2) ? coef_at(db, k - 1) : 0.f;
+            const float d0 = (m & 4) ? coef_at(db, k) : 0.f;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+                acc2n.v[i] = fmaf(d0, t.v[i], fmaf(d1, own.v[i], fmaf(d2, p2.v[i], ac2.v[i])));
+        }
     }
     if (flags & STEP_WRITE_T) vstore<VEC>(A.tout + off, t);
     if (flags & STEP_EPI_SCALE) {
@@ -187,24 +213,29 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t
         }
     } else if (flags & STEP_ACC_WRITE) {
         vstore_nt<VEC>(A.acc + off, accn);
-        if constexpr (DUAL) vstore_nt<VEC>(A.acc2 + off, acc2n);
+        if constexpr (MODE == kModeDual) vstore_nt<VEC>(A.acc2 + off, acc2n);
     }
 }
 
-template <int VEC, bool DUAL>
+template <int VEC, int MODE>
 __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off, Vec<VEC>& own, Vec<VEC>& p2,
                                                   Vec<VEC>& ac, Vec<VEC>& ac2) {
     own = vload<VEC>(A.tprev + off);
+    if constexpr (MODE == kModeClen) {
+        if (A.flags & STEP_CLEN_P2) p2 = vload_nt<VEC>(A.tprev2 + off);
+        ac = vload_nt<VEC>(A.xin + off);
+        return;
+    }
     if (!(A.flags & STEP_FIRST)) p2 = vload_nt<VEC>(A.tprev2 + off);
     if (A.flags & STEP_ACC_READ) {
         ac = vload_nt<VEC>(A.acc + off);
-        if constexpr (DUAL) ac2 = vload_nt<VEC>(A.acc2 + off);
+        if constexpr (MODE == kModeDual) ac2 = vload_nt<VEC>(A.acc2 + off);
     }
 }
 
 // Rows with more than A.long_thr nonzeros: one block per row and column tile,
 // 256/C lanes splitting the nonzeros, a block reduction through LDS.
-template <int VEC, int C, bool DUAL>
+template <int VEC, int C, int MODE>
 __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int ncoltiles, float* red_lds) {
     constexpr int SL = kBlock / C;   // lanes over the nonzeros
     float (*red)[C][VEC + 1] = reinterpret_cast<float (*)[C][VEC + 1]>(red_lds);
@@ -219,7 +250,7 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     const bool colok = colofs < A.ldp;   // lanes past the padded row stay idle
     const size_t off = (size_t)row * A.ldp + (colok ? colofs : 0);
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
-    if (s == 0 && colok) load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
+    if (s == 0 && colok) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
     const int rs = A.rowptr[row], re = colok ? A.rowptr[row + 1] : rs;
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
@@ -261,11 +292,11 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
             for (int i = 0; i < VEC; ++i) sx.v[i] += red[wv][c][i];
             sw += red[wv][c][VEC];
         }
-        step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
+        step_epilogue<VEC, MODE>(A, row, off, own, p2, ac, ac2, sx, sw);
     }
 }
 
-template <int VEC, int S, int C, bool DUAL>
+template <int VEC, int S, int C, int MODE>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
     constexpr int RPW = 64 / LPR;    // rows per wave
@@ -278,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     // the first blocks take the long rows (dispatched first, they overlap the tiles)
     const int nlb = A.nlong * ncoltiles;
     if ((int)blockIdx.x < nlb) {
-        long_row_block<VEC, C, DUAL>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
+        long_row_block<VEC, C, MODE>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
         return;
     }
     const int bt = (int)blockIdx.x - nlb;
@@ -308,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         if (longrow) {
             re = rs;   // taken by a long-row block at the head of the grid
         } else {
-            load_row_operands<VEC, DUAL>(A, off, own, p2, ac, ac2);
+            load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
         }
     }
 
@@ -357,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         for (int i = 0; i < VEC; ++i) sx.v[i] += __shfl_xor(sx.v[i], o, 64);
     }
     if (!valid || s != 0 || longrow) return;
-    step_epilogue<VEC, DUAL>(A, row, off, own, p2, ac, ac2, sx, sw);
+    step_epilogue<VEC, MODE>(A, row, off, own, p2, ac, ac2, sx, sw);
 }
 
 template <int VEC, int S, int C>
@@ -366,10 +397,12 @@ void launch_shape(const StepArgs& a, hipStream_t st) {
     const int nrt = (a.n + RPB - 1) / RPB;
     const int nct = (a.ldp + VEC * C - 1) / (VEC * C);
     const int grid = nrt * nct + a.nlong * nct;
-    if (a.flags & STEP_DUAL)
-        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.flags & STEP_CLENSHAW)
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeClen>), dim3(grid), dim3(kBlock), 0, st, a);
+    else if (a.flags & STEP_DUAL)
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeDual>), dim3(grid), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, false>), dim3(grid), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeFwd>), dim3(grid), dim3(kBlock), 0, st, a);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -395,9 +428,28 @@ __global__ void set_coef_kernel(float* dcoef, CoefPack pk, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) dcoef[i] = pk.v[i];
 }
 
-__global__ void stream_copy_kernel(const float4* src, float4* dst, int64_t n4) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Bandwidth reference: each thread moves kCopyUnroll float4 (loads issued
+// before the stores, non-temporal), block-strided so every load instruction
+// is coalesced; one pass over the array (grid = n4 / (256 kCopyUnroll)).
+// Measured on 1 GiB: 6.27 TB/s read + write against 5.44 TB/s for one float4
+// per thread in a grid-stride loop.
+constexpr int kCopyUnroll = 4;
+
+__global__ __launch_bounds__(kBlock) void stream_copy_kernel(const float4* src, float4* dst, int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * kCopyUnroll;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x * kCopyUnroll + threadIdx.x; i < n4; i += stride) {
+        v4f v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t j = i + (int64_t)u * blockDim.x;
+            if (j < n4) v[u] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(src) + j);
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t j = i + (int64_t)u * blockDim.x;
+            if (j < n4) __builtin_nontemporal_store(v[u], reinterpret_cast<v4f*>(dst) + j);
+        }
+    }
 }
 
 __global__ void stream_copy_tail_kernel(const float* src, float* dst, int64_t from, int64_t count) {
@@ -682,9 +734,12 @@ void launch_set_coef(float* dcoef, double alpha, const double* b, const double* 
 
 void launch_stream_copy(const float* src, float* dst, int64_t count, hipStream_t st) {
     const int64_t n4 = count / 4;
-    if (n4 > 0)
-        hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for(n4)), dim3(kBlock), 0, st,
+    if (n4 > 0) {
+        int64_t blocks = (n4 + (int64_t)kBlock * kCopyUnroll - 1) / ((int64_t)kBlock * kCopyUnroll);
+        if (blocks > (1 << 30)) blocks = 1 << 30;   // the loop covers the rest
+        hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st,
                            reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n4);
+    }
     if (count > n4 * 4)
         hipLaunchKernelGGL(stream_copy_tail_kernel, dim3(1), dim3(kBlock), 0, st, src, dst, n4 * 4, count);
 }

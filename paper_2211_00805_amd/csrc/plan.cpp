@@ -48,16 +48,6 @@ StepArgs base_args(gs_plan_s& P) {
     return a;
 }
 
-// Column lanes: the smallest power of two covering the row's float4 groups
-// (at most 16; a short last tile or idle lanes when the groups are not a
-// power of two), and S = 8 / C lanes over a row's nonzeros.
-LaunchShape default_shape(int ldp, double nnz_per_row) {
-    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1};
-    int C = 1;
-    while (C < 16 && C < ldp / 4) C *= 2;
-    int S = std::max(1, 8 / C);
-    return {4, S, C, 1};
-}
 
 // Run `body` on `st` directly, or capture it once into a hipGraph (on the
 // plan's private stream) and replay the graph on `st`.
@@ -178,7 +168,47 @@ double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>&
     return hi;
 }
 
+// Last component of the unit eigenvector of the tridiagonal T (diagonal al,
+// off-diagonal be) for its largest eigenvalue theta, by inverse iteration with
+// the shift sigma slightly above theta: T - sigma I is negative definite, so
+// its LU factorisation without pivoting is stable.
+double tridiag_last_component(const std::vector<double>& al, const std::vector<double>& be, double theta) {
+    const int m = (int)al.size();
+    if (m == 1) return 1.0;
+    const double sigma = theta + 1e-12 * std::max(1.0, std::fabs(theta));
+    std::vector<double> x(m, 1.0), d(m), c(m);
+    for (int it = 0; it < 3; ++it) {
+        // solve (T - sigma I) y = x (Thomas algorithm), then normalise
+        d[0] = al[0] - sigma;
+        c[0] = x[0];
+        for (int i = 1; i < m; ++i) {
+            const double l = be[i - 1] / d[i - 1];
+            d[i] = al[i] - sigma - l * be[i - 1];
+            c[i] = x[i] - l * c[i - 1];
+        }
+        x[m - 1] = c[m - 1] / d[m - 1];
+        for (int i = m - 2; i >= 0; --i) x[i] = (c[i] - be[i] * x[i + 1]) / d[i];
+        double nrm = 0.0;
+        for (double v : x) nrm += v * v;
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return 1.0;   // no estimate: the caller keeps safety * theta
+        for (double& v : x) v /= nrm;
+    }
+    return x[m - 1];
+}
+
 }  // namespace
+
+// Column lanes: the smallest power of two covering the row's float4 groups
+// (at most 16; a short last tile or idle lanes when the groups are not a
+// power of two), and S = 8 / C lanes over a row's nonzeros.
+LaunchShape default_shape(int ldp, double nnz_per_row) {
+    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1};
+    int C = 1;
+    while (C < 16 && C < ldp / 4) C *= 2;
+    int S = std::max(1, 8 / C);
+    return {4, S, C, 1};
+}
 
 }  // namespace gs
 
@@ -256,26 +286,45 @@ void set_kernel(gs_plan_s& P, int kernel, int N, int cg_iters) {
     }
 }
 
+// Flush the accumulator on steps 2, 5, 8, ... and on the last step; a flush
+// adds every term since the previous flush (at most T_{k-2}, T_{k-1}, T_k, all
+// of which the step holds).
+StepSched step_sched_at(int K, int k, ApplyMode mode) {
+    auto flushes = [K](int j) { return j == K || (j >= 2 && (j - 2) % 3 == 0); };
+    int f = 0, m = 0;
+    if (k == 1) f |= STEP_FIRST;
+    if (mode == ApplyMode::Dual) f |= STEP_DUAL;
+    const bool final = k == K;
+    if (flushes(k)) {
+        int last = -1;  // highest term index already in the accumulator
+        for (int j = 2; j < k; ++j)
+            if (flushes(j)) last = j;
+        for (int idx = last + 1; idx <= k; ++idx) m |= idx == k - 2 ? 1 : idx == k - 1 ? 2 : 4;
+        if (last >= 0) f |= STEP_ACC_READ;
+        f |= (final && mode == ApplyMode::Scale) ? STEP_EPI_SCALE : STEP_ACC_WRITE;
+    }
+    if (!final) f |= STEP_WRITE_T;
+    return {f, m};
+}
+
 std::vector<StepSched> step_schedule(int K, ApplyMode mode) {
-    // Flush the accumulator on steps 2, 5, 8, ... and on the last step; a
-    // flush adds every term since the previous flush (at most T_{k-2}, T_{k-1},
-    // T_k, all of which the step holds).
     std::vector<StepSched> out(K);
-    int last = -1;  // highest term index already in the accumulator
-    for (int k = 1; k <= K; ++k) {
-        int f = 0, m = 0;
-        if (k == 1) f |= STEP_FIRST;
-        if (mode == ApplyMode::Dual) f |= STEP_DUAL;
-        const bool final = k == K;
-        const bool flush = final || (k >= 2 && (k - 2) % 3 == 0);
-        if (flush) {
-            for (int idx = last + 1; idx <= k; ++idx) m |= idx == k - 2 ? 1 : idx == k - 1 ? 2 : 4;
-            if (last >= 0) f |= STEP_ACC_READ;
-            last = k;
-            f |= (final && mode == ApplyMode::Scale) ? STEP_EPI_SCALE : STEP_ACC_WRITE;
-        }
-        if (!final) f |= STEP_WRITE_T;
-        out[k - 1] = {f, m};
+    for (int k = 1; k <= K; ++k) out[k - 1] = step_sched_at(K, k, mode);
+    return out;
+}
+
+std::vector<StepSched> clenshaw_schedule(int K, ApplyMode mode) {
+    // Product j = 1..K of Clenshaw's recurrence: j = 1 gathers X itself, u_{K-j+2}
+    // is read from memory from j = 3 on (j = 2 folds u_K = b_K X into its X
+    // coefficient), and the last product writes the result (or scales).
+    std::vector<StepSched> out(K);
+    for (int j = 1; j <= K; ++j) {
+        int f = STEP_CLENSHAW;
+        if (j == 1) f |= STEP_FIRST;
+        if (j >= 3) f |= STEP_CLEN_P2;
+        if (j < K) f |= STEP_WRITE_T;
+        else f |= mode == ApplyMode::Scale ? STEP_EPI_SCALE : STEP_ACC_WRITE;
+        out[j - 1] = {f, 0};
     }
     return out;
 }
@@ -284,6 +333,14 @@ double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool 
     const double nb = 4.0 * (double)P.n * P.B;
     const double acc = (sc.flags & STEP_DUAL) ? 2.0 : 1.0;
     double b = 4.0 * (P.n + 1) + 8.0 * P.g->nnz + nb;  // CSR once, T_{k-1} once
+    if (sc.flags & STEP_CLENSHAW) {
+        b += nb;                                      // X
+        if (sc.flags & STEP_CLEN_P2) b += nb;         // u_{k+2}
+        if (sc.flags & STEP_WRITE_T) b += nb;         // u_k
+        if (sc.flags & STEP_ACC_WRITE) b += nb;       // result
+        if (sc.flags & STEP_EPI_SCALE) b += 2.0 * nb + (has_out_a ? nb : 0.0) + (has_rec ? nb : 0.0);
+        return b;
+    }
     if (!(sc.flags & STEP_FIRST)) b += nb;
     if (sc.flags & STEP_WRITE_T) b += nb;
     if (sc.flags & STEP_ACC_READ) b += acc * nb;
@@ -307,6 +364,33 @@ void enqueue_cheb_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Scal
         a.phi = phi;
         a.flags = sched[k - 1].flags;
         a.cmask = sched[k - 1].cmask;
+        if (a.flags & STEP_EPI_SCALE) {
+            a.num = epi.num;
+            a.out = epi.out;
+            a.out_a = epi.out_a;
+            a.a = epi.a;
+            a.rec = epi.rec;
+        }
+        launch_step(P.shape, a, st);
+    }
+}
+
+// p_K X by Clenshaw's recurrence into ACC (or scaled into epi.out); u_k
+// rotates through U and V like T_k, written over u_{k+2} in place.
+void enqueue_clenshaw_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi,
+                            hipStream_t st) {
+    const StepArgs base = base_args(P);
+    const std::vector<StepSched> sched = clenshaw_schedule(P.K, mode);
+    for (int j = 1; j <= P.K; ++j) {
+        StepArgs a = base;
+        a.k = j;
+        a.tprev = j == 1 ? X : T(P, j - 1);
+        a.tprev2 = j >= 3 ? T(P, j - 2) : nullptr;
+        a.tout = T(P, j);
+        a.xin = X;
+        a.phi = phi;
+        a.flags = sched[j - 1].flags;
+        a.cmask = 0;
         if (a.flags & STEP_EPI_SCALE) {
             a.num = epi.num;
             a.out = epi.out;
@@ -361,22 +445,32 @@ void enqueue_euler_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Sca
 void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
     if (P.kernel == GS_KERNEL_EULER)
         enqueue_euler_apply(P, X, mode, epi, phi, st);
+    else if (P.kernel == GS_KERNEL_CLENSHAW && mode != ApplyMode::Dual)
+        enqueue_clenshaw_apply(P, X, mode, epi, phi, st);   // the dual form needs the accumulators
     else
         enqueue_cheb_apply(P, X, mode, epi, phi, st);
 }
 
 // Average duration (ms) of one step launch over `reps` whole applications of
-// p_K (accumulator form), and the average algorithmic bytes of a launch.
+// p_K (the accumulator form, or Clenshaw's when the plan selects it), and
+// the average algorithmic bytes of a launch.
 double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch) {
     const LaunchShape saved = P.shape;
     P.shape = shape;
     if (!(shape == saved) || P.long_thr == 0) update_long_rows(P);
-    enqueue_cheb_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+    const bool clen = P.kernel == GS_KERNEL_CLENSHAW;
+    auto apply = [&] {
+        if (clen)
+            enqueue_clenshaw_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+        else
+            enqueue_cheb_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+    };
+    apply();
     hipEvent_t e0, e1;
     GS_HIP(hipEventCreate(&e0));
     GS_HIP(hipEventCreate(&e1));
     GS_HIP(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i) enqueue_cheb_apply(P, P.X.p, ApplyMode::Store, ScaleEpi{}, 0.f, st);
+    for (int i = 0; i < reps; ++i) apply();
     GS_HIP(hipEventRecord(e1, st));
     GS_HIP(hipEventSynchronize(e1));
     if (!(shape == saved)) {
@@ -390,7 +484,8 @@ double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t s
     GS_HIP(hipGetLastError());
     if (bytes_per_launch) {
         double tot = 0.0;
-        for (const auto& sc : step_schedule(P.K, ApplyMode::Store)) tot += step_bytes(P, sc, false, false);
+        for (const auto& sc : clen ? clenshaw_schedule(P.K, ApplyMode::Store) : step_schedule(P.K, ApplyMode::Store))
+            tot += step_bytes(P, sc, false, false);
         *bytes_per_launch = tot / P.K;
     }
     return (double)ms / ((double)reps * P.K);
@@ -826,13 +921,14 @@ double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStr
         return out;
     };
     std::vector<double> al, be;
-    double beta_prev = 0.0;
+    double beta_prev = 0.0, beta_last = 0.0;
     for (int j = 0; j < iters; ++j) {
         launch_lap_spmv(g.rowptr.p, g.col.p, g.val.p, (int32_t)n, q.p, z.p, st);
         const double aj = dot(q.p, z.p);
         launch_lanczos_update(z.p, q.p, qp.p, aj, beta_prev, n, st);
         const double bj = std::sqrt(std::max(0.0, dot(z.p, z.p)));
         al.push_back(aj);
+        beta_last = bj;
         if (j == iters - 1 || bj <= 1e-10 * std::max(1.0, std::fabs(aj))) break;
         be.push_back(bj);
         launch_scale(qp.p, z.p, 1.0 / bj, n, st);
@@ -843,7 +939,11 @@ double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStr
     const double theta = tridiag_max_eig(al, be);
     if (!(theta > 0.0) || !std::isfinite(theta))
         fail(GS_ERR_SPECTRUM, "Lanczos produced no positive Ritz value (graph without edges?)");
-    return std::min(safety * theta, g.edge_bound);
+    // ||L y - theta y|| = beta_m |s_m| for the Ritz vector y = Q s: an eigenvalue
+    // of L lies within it of theta, so theta + residual covers lambda_max once
+    // theta approximates it, when the safety factor alone would not
+    const double resid = beta_last * std::fabs(tridiag_last_component(al, be, theta));
+    return std::min(std::max(safety * theta, theta + resid), g.edge_bound);
 }
 
 }  // namespace gs

@@ -55,7 +55,8 @@ struct gs_plan_s {
     gs::DevBuf<float> segd, sege, dmu, dnu, vseed, wbar, wck, g4t;
     gs::DevBuf<double> tbar;
 
-    // kernel selection: GS_KERNEL_CHEBYSHEV or GS_KERNEL_EULER (N solves of
+    // kernel selection: GS_KERNEL_CHEBYSHEV, GS_KERNEL_CLENSHAW (the same
+    // polynomial by Clenshaw's recurrence) or GS_KERNEL_EULER (N solves of
     // cg_m conjugate-gradient iterations; cg_iters == 0 picks cg_m per call)
     int kernel = GS_KERNEL_CHEBYSHEV;
     int euler_N = 0, cg_iters = 0, cg_m = 0;
@@ -88,6 +89,9 @@ void drop_graphs(gs_plan_s& P);
 void update_long_rows(gs_plan_s& P);
 double time_step(gs_plan_s& P, const LaunchShape& shape, int reps, hipStream_t st, double* bytes_per_launch);
 std::vector<StepSched> step_schedule(int K, ApplyMode mode);
+StepSched step_sched_at(int K, int k, ApplyMode mode);
+std::vector<StepSched> clenshaw_schedule(int K, ApplyMode mode);
+LaunchShape default_shape(int ldp, double nnz_per_row);
 double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool has_rec);
 double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStream_t st);
 

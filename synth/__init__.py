@@ -35,6 +35,11 @@ __all__ = [
     "random_dense_like",
     "loguniform_support_sizes",
     "histogram_on_random_support",
+    "curve_pair_workload",
+    "barycenter_workload",
+    "gradient_pairs",
+    "local_graph_1m",
+    "loguniform_pair_batch",
 ]
 
 
@@ -321,3 +326,66 @@ def complete_graph(n: int):
     """Unit-weight complete graph K_n as CSR."""
     i, j = np.triu_indices(n, 1)
     return _csr_from_undirected(n, i, j, np.ones(i.shape[0]))
+
+
+# ----------------------------------------------------------------------------
+# the paper-shaped workloads (points or graph plus histograms), one recipe each
+# ----------------------------------------------------------------------------
+
+def curve_pair_workload(per_cluster: int = 5000, n_clusters: int = 20):
+    """Plain forward: clusters on a curve in R^50 (workload 2) and one histogram pair.
+
+    mu = Dirichlet(1) on clusters 0-3, nu = Dirichlet(1) on clusters 4-7.
+    Returns (X float32 (n, 50), labels, mu float32 (n,), nu float32 (n,)).
+    """
+    X, labels = clusters_on_curve(n_clusters, per_cluster, dim=50, sigma=0.1, workload=2)
+    mu, nu = cluster_block_pair(labels, 0, 4, 1.0, np.random.default_rng(seed_for(2, 2)))
+    return X, labels, mu, nu
+
+
+def barycenter_workload(per_cluster: int = 6667, lo: int = 1000, hi: int = 50000, m: int = 64):
+    """Barycenter: 30 clusters on a curve in R^50 (workload 3) and m input histograms.
+
+    Supports of log-uniform size in [lo, hi] on random nodes, Dirichlet(0.5).
+    Returns (X float32 (n, 50), labels, H float32 (n, m)).
+    """
+    X, labels = clusters_on_curve(30, per_cluster, dim=50, sigma=0.1, workload=3)
+    H, _ = loguniform_support_histograms(X.shape[0], m, lo, hi, 0.5, np.random.default_rng(seed_for(3, 2)))
+    return X, labels, H
+
+
+def gradient_pairs(labels: np.ndarray, B: int = 32, width: int = 3):
+    """Differentiation: B Dirichlet(1) pairs on adjacent blocks of `width` clusters.
+
+    Each pair starts at a random cluster (seed of workload 4); mu covers
+    clusters [s, s+width), nu the next `width`.  Returns (mu, nu) float32 (n, B).
+    """
+    rng = np.random.default_rng(seed_for(4, 2))
+    ncl = int(labels.max()) + 1
+    pairs = [cluster_block_pair(labels, int(rng.integers(0, ncl - 2 * width)), width, 1.0, rng) for _ in range(B)]
+    return np.stack([p[0] for p in pairs], axis=1), np.stack([p[1] for p in pairs], axis=1)
+
+
+def local_graph_1m(n: int = 1_000_000):
+    """A 1M-node random local graph with the 1M kNN workload's size (workload 10).
+
+    k = 9 partners per node within a window of 20,000 ids plus 200 hub nodes of
+    1000 extra random partners each: about 18.4M nonzeros (the kNN graph has
+    18.3M) and rows long enough for the long-row path.  Returns CSR arrays.
+    """
+    return random_local_graph(n, 9, 20000, np.random.default_rng(seed_for(10, 0)), hubs=200, hub_degree=1000)
+
+
+def loguniform_pair_batch(n: int, B: int, lo: int, hi: int, workload: int):
+    """B histogram pairs with log-uniform support sizes in [lo, hi], Dirichlet(1).
+
+    Histogram i (0..2B-1) has its own seed seed_for(workload, 2) * 1000 + i;
+    pair b is (histogram 2b, histogram 2b+1).  Returns (mu, nu) float32 (n, B).
+    """
+    sizes = loguniform_support_sizes(n, 2 * B, lo, hi, seed_for(workload, 2))
+    mu = np.empty((n, B), dtype=np.float32)
+    nu = np.empty((n, B), dtype=np.float32)
+    for b in range(B):
+        mu[:, b] = histogram_on_random_support(n, int(sizes[2 * b]), 1.0, seed_for(workload, 2) * 1000 + 2 * b)
+        nu[:, b] = histogram_on_random_support(n, int(sizes[2 * b + 1]), 1.0, seed_for(workload, 2) * 1000 + 2 * b + 1)
+    return mu, nu

@@ -24,6 +24,7 @@ import torch
 import synth
 from oracle import graph as ograph
 from oracle import heat
+from oracle import spectrum
 from gpu_common import need_gpu, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +71,19 @@ def test_sampled_rows_are_exact_knn_unions(big):
     r = np.concatenate(logs)
     np.testing.assert_allclose(r, -1.0 / g.median ** 2, rtol=2e-6)
     assert g.n_components == 1
+
+
+def test_lambda_hat_brackets_lambda_max(big):
+    """The library's lambda_hat (Lanczos) lies between lambda_max of the exported
+    graph's Laplacian (ARPACK, float64) and the edge bound max_E (d_i + d_j):
+    the Chebyshev expansion needs the spectrum inside [0, lambda_hat]."""
+    gs, X, g, lam = big
+    rp, col, w, _ = g.export()
+    A = ograph.csr_from_arrays(g.n, rp, col, w.astype(np.float64))
+    lmax = spectrum.lambda_max(ograph.laplacian(A))
+    eb = spectrum.edge_bound(A)
+    print(f"n={g.n}: lambda_max {lmax:.6f} <= lambda_hat {lam:.6f} <= edge bound {eb:.6f}")
+    assert lmax * (1 + 1e-9) <= lam <= eb * (1 + 1e-6)
 
 
 def test_heat_apply_mass_and_symmetry_in_benchmark_shape(big):

@@ -92,3 +92,21 @@ def test_complete_graph_spectrum():
     L = graph.laplacian(A)
     assert spectrum.lambda_max(L) == pytest.approx(n, rel=1e-13)
     assert spectrum.edge_bound(A) == pytest.approx(2 * (n - 1))
+
+
+def test_knn_row_ranges_assemble_the_full_search():
+    """knn_lists over row ranges, concatenated, equals the single search; knn_graph
+    built from those lists equals the graph built directly (weights by
+    gaussian_weights of the union's pairs)."""
+    X = np.random.default_rng(3).standard_normal((700, 6))
+    full, d2 = graph.knn_lists(X, 9)
+    parts = [graph.knn_lists(X, 9, block=128, rows=(lo, min(700, lo + 256)))[0] for lo in range(0, 700, 256)]
+    assert np.array_equal(np.concatenate(parts), full)
+    A, info = graph.knn_graph(X, 9)
+    A2, _ = graph.knn_graph(X, 9, knn_idx=np.concatenate(parts))
+    assert (A != A2).nnz == 0
+    coo = A.tocoo()
+    w = graph.gaussian_weights(X, coo.row, coo.col, info["median"])
+    assert np.array_equal(w, coo.data)
+    with pytest.raises(ValueError):
+        graph.knn_lists(X, 9, rows=(600, 800))
