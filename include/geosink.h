@@ -347,6 +347,36 @@ gs_status gs_accumulate_columns(const float* src, int64_t n, int32_t B, const in
 gs_status gs_plan_time_step(gs_plan p, int32_t reps, hipStream_t stream, double* avg_ms,
                             double* bytes_per_launch);
 
+/* ------------------------------------------------------------------------ */
+/* Entry point that allocates nothing                                         */
+/* ------------------------------------------------------------------------ */
+
+#define GS_NOALLOC_MAX_NB (4 << 20) /* largest n * B of gs_heat_apply_noalloc */
+
+/* For callers that cannot allocate device memory: code under hipGraph stream
+ * capture, serving loops and harnesses that forbid hipMalloc.
+ * Y = p_K(L, t) X as gs_heat_apply computes it (the same accumulating
+ * Chebyshev steps and kernel), without a plan: the two n x B Chebyshev buffers
+ * and the coefficient table live in a file-scope device array of
+ * 2 * GS_NOALLOC_MAX_NB + 1024 floats (32 MiB) that each GPU the library runs
+ * on holds until the process ends; X is read in place and Y is the
+ * accumulator.  No hipMalloc, hipFree, memset, host synchronisation or
+ * allocating library call is made, so the call can be captured into a
+ * hipGraph; its first call on a device resolves the array's address there
+ * (make one call outside capture first).
+ *   g          graph on the current device;
+ *   lambda_hat > 0 (finite), t >= 0 (finite), 1 <= K <= GS_MAX_K;
+ *   X, Y       device n x B float32, node-major (ld = B), distinct;
+ *   B          1 or a multiple of 4, with n * B <= GS_NOALLOC_MAX_NB
+ *              (GS_ERR_INVALID beyond it, checked before any device work).
+ * Default launch shape, every row in the row-group kernel (no long-row
+ * blocks).  Every call on one GPU shares that GPU's array and keeps the last
+ * call's contents (each call writes all it reads): calls that overlap on one
+ * device (two streams, two host threads) race on it and must be ordered by
+ * the caller.  Asynchronous on `stream`. */
+gs_status gs_heat_apply_noalloc(gs_graph g, double lambda_hat, double t, int32_t K, const float* X, float* Y,
+                                int32_t B, hipStream_t stream);
+
 /* dst[i] = src[i] for i < count (device float32) with a plain streaming copy
  * kernel; a bandwidth reference for the step kernel. */
 gs_status gs_stream_copy(const float* src, float* dst, int64_t count, hipStream_t stream);

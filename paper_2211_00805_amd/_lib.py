@@ -62,6 +62,8 @@ _SIGS = {
     "gs_plan_describe": (C.c_int, [c_plan, C.c_char_p, C.c_int32]),
     "gs_plan_destroy": (None, [c_plan]),
     "gs_heat_apply": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f32, c_stream]),
+    "gs_heat_apply_noalloc": (C.c_int, [c_graph, C.c_double, C.c_double, C.c_int32, P_f32, P_f32, C.c_int32,
+                                        c_stream]),
     "gs_sinkhorn": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f32, C.c_int32, C.c_float,
                               C.c_int32, P_f32, P_f32, P_f32, P_f64, P_f64, P_i64, c_stream]),
     "gs_sinkhorn_backward": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f32, C.c_int32, C.c_float,

@@ -21,7 +21,7 @@ __all__ = [
     "Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH", "GS_KERNEL_CHEBYSHEV", "GS_KERNEL_CLENSHAW", "GS_KERNEL_EULER",
     "GS_RECORD_ALL", "ckpt_floats",
     "gs_abi_version", "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs",
-    "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_sinkhorn", "gs_sinkhorn_backward",
+    "gs_cheby_tail_bound", "gs_plan_create", "gs_heat_apply", "gs_heat_apply_noalloc", "gs_sinkhorn", "gs_sinkhorn_backward",
     "gs_barycenter", "gs_expectation", "gs_gather_columns", "gs_accumulate_columns", "gs_plan_time_step", "gs_stream_copy", "gs_stream_gather", "current_stream",
 ]
 
@@ -194,6 +194,22 @@ def gs_heat_apply(plan: Plan, lambda_hat: float, t: float, X: torch.Tensor, Y: t
     nb = _nB(plan)
     check("gs_heat_apply", lib.gs_heat_apply(plan.handle, float(lambda_hat), float(t), _dev(X, "X", nb),
                                              _dev(Y, "Y", nb), _dev(Ydt, "Ydt", nb), current_stream()))
+
+
+def gs_heat_apply_noalloc(graph: Graph, lambda_hat: float, t: float, K: int, X: torch.Tensor,
+                          Y: torch.Tensor) -> None:
+    """Y = p_K(L, t) X without a plan or any allocation (X, Y: n x B, B = 1 or a multiple of 4)."""
+    if X.dim() == 1:
+        B = 1
+    elif X.dim() == 2:
+        B = X.shape[1]
+    else:
+        raise ValueError("X must be (n,) or (n, B)")
+    if X.shape[0] != graph.n or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold n x B floats")
+    check("gs_heat_apply_noalloc", lib.gs_heat_apply_noalloc(
+        graph.handle, float(lambda_hat), float(t), int(K), _dev(X, "X", X.numel()), _dev(Y, "Y", Y.numel()),
+        int(B), current_stream()))
 
 
 def n_checkpoints(iters: int, ckpt_every: int) -> int:

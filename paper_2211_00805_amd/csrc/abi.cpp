@@ -242,6 +242,22 @@ gs_status gs_heat_apply(gs_plan p, double lambda_hat, double t, const float* X, 
     });
 }
 
+gs_status gs_heat_apply_noalloc(gs_graph g, double lambda_hat, double t, int32_t K, const float* X, float* Y,
+                                int32_t B, hipStream_t stream) {
+    return guarded([&] {
+        GS_REQUIRE(g != nullptr, "graph is NULL");
+        GS_REQUIRE(std::isfinite(lambda_hat) && lambda_hat > 0.0, "lambda_hat must be finite and > 0");
+        GS_REQUIRE(std::isfinite(t) && t >= 0.0, "t must be finite and >= 0");
+        GS_REQUIRE(K >= 1 && K <= GS_MAX_K, "K must be in [1, GS_MAX_K]");
+        GS_REQUIRE(B == 1 || (B >= 4 && B % 4 == 0), "B must be 1 or a multiple of 4");
+        GS_REQUIRE(g->n * (int64_t)B <= (int64_t)GS_NOALLOC_MAX_NB,
+                   "n * B exceeds GS_NOALLOC_MAX_NB (the fixed scratch array of the no-allocation entry point)");
+        GS_REQUIRE(X != nullptr && Y != nullptr, "X / Y is NULL");
+        GS_REQUIRE((const float*)Y != X, "X and Y must be distinct");
+        heat_apply_noalloc(*g, lambda_hat, t, K, X, Y, B, stream);
+    });
+}
+
 gs_status gs_sinkhorn(gs_plan p, double lambda_hat, double t, const float* a, const float* mu, const float* nu,
                       int32_t iters, float phi, int32_t ckpt_every, float* ckpt, float* v, float* w, double* dist,
                       double* marg_err, int64_t* n_floored, hipStream_t stream) {

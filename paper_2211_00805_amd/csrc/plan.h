@@ -92,6 +92,7 @@ std::vector<StepSched> step_schedule(int K, ApplyMode mode);
 StepSched step_sched_at(int K, int k, ApplyMode mode);
 std::vector<StepSched> clenshaw_schedule(int K, ApplyMode mode);
 LaunchShape default_shape(int ldp, double nnz_per_row);
+void heat_apply_noalloc(gs_graph_s& g, double lam, double t, int K, const float* X, float* Y, int B, hipStream_t st);
 double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool has_rec);
 double lambda_max(gs_graph_s& g, int iters, uint64_t seed, double safety, hipStream_t st);
 
