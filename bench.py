@@ -99,8 +99,8 @@ TUNE_CACHE = os.path.join(ROOT, "paper_2211_00805_amd", "tune_cache.json")
 
 
 def shape_key(desc: str) -> str:
-    """The launch-shape part of a plan description (vec, S, C, XCD order, ldp)."""
-    return " ".join(w for w in desc.split() if w.split("=")[0] in ("vec", "S", "C", "xcd", "ldp"))
+    """The launch-shape part of a plan description (vec, S, C, XCD order, CSR hint, ldp)."""
+    return " ".join(w for w in desc.split() if w.split("=")[0] in ("vec", "S", "C", "xcd", "csr", "ldp"))
 
 
 def measured_traffic(shape_desc: str, n: int, nnz: int, B: int):

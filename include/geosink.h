@@ -164,6 +164,15 @@ gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const 
  * Cached hipGraphs of the plan are dropped. */
 gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C);
 
+/* How the step kernel reads the graph's CSR arrays: streamed = 1 with
+ * non-temporal hints (a CSR larger than the caches passes once per step and
+ * leaves L2 to the gathered rows), 0 with ordinary cached loads (a CSR that
+ * fits the caches stays there across the K steps).  The autotuner chooses it
+ * with the launch shape (GS_PLAN_AUTOTUNE); this call overrides it (tuning
+ * studies, tests).  Results are bitwise the same either way.  Cached hipGraphs
+ * of the plan are dropped; synchronises the device. */
+gs_status gs_plan_set_csr_hint(gs_plan p, int32_t streamed);
+
 /* Kernel a plan applies in gs_heat_apply, gs_sinkhorn and gs_barycenter. */
 #define GS_KERNEL_CHEBYSHEV 0 /* p_K(L, t): degree-K Chebyshev sum (default) */
 #define GS_KERNEL_EULER 1     /* backward-Euler (I + (t/N) L_op)^{-N}       */

@@ -160,6 +160,10 @@ class Plan:
         """gs_plan_set_shape: force the fused step's launch shape."""
         check("gs_plan_set_shape", lib.gs_plan_set_shape(self.handle, int(vec), int(S), int(C_)))
 
+    def set_csr_hint(self, streamed: bool) -> None:
+        """gs_plan_set_csr_hint: CSR read with non-temporal hints (streamed) or with cached loads."""
+        check("gs_plan_set_csr_hint", lib.gs_plan_set_csr_hint(self.handle, int(bool(streamed))))
+
     def set_kernel(self, kernel: int, N: int = 0, cg_iters: int = 0) -> None:
         """gs_plan_set_kernel: Chebyshev (default) or backward-Euler (N solves of cg_iters CG steps, 0 = auto)."""
         check("gs_plan_set_kernel", lib.gs_plan_set_kernel(self.handle, int(kernel), int(N), int(cg_iters)))

@@ -185,7 +185,7 @@ gs_status gs_plan_create(gs_graph g, int32_t K, int32_t B, int32_t flags, const 
 gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr, "plan is NULL");
-        const LaunchShape s{vec, S, C, p->shape.remap};
+        const LaunchShape s{vec, S, C, p->shape.remap, p->shape.csr_nt};
         GS_REQUIRE(shape_supported(s), "unsupported launch shape");
         GS_REQUIRE((vec == 1) == (p->ldp == 1), "vec must be 1 exactly when B == 1");
         GS_REQUIRE(column_lanes_ok(p->ldp, vec, C), "C must be 1 or below twice the padded B's float4 groups");
@@ -194,6 +194,17 @@ gs_status gs_plan_set_shape(gs_plan p, int32_t vec, int32_t S, int32_t C) {
         p->shape = s;
         p->shape_origin = "set";
         update_long_rows(*p);
+    });
+}
+
+gs_status gs_plan_set_csr_hint(gs_plan p, int32_t streamed) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr, "plan is NULL");
+        GS_REQUIRE(streamed == 0 || streamed == 1, "streamed must be 0 or 1");
+        GS_HIP(hipDeviceSynchronize());
+        drop_graphs(*p);
+        p->shape.csr_nt = streamed;
+        p->shape_origin = "set";
     });
 }
 
@@ -216,6 +227,7 @@ gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len) {
         GS_REQUIRE(p != nullptr && buf != nullptr && len > 0, "bad arguments");
         const std::string s = "vec=" + std::to_string(p->shape.vec) + " S=" + std::to_string(p->shape.S) +
                               " C=" + std::to_string(p->shape.C) + " xcd=" + std::to_string(p->shape.remap) +
+                              (p->shape.csr_nt ? " csr=nt" : " csr=t") +
                               " ldp=" + std::to_string(p->ldp) +
                               " origin=" + p->shape_origin + ((p->flags & GS_PLAN_NO_GRAPH) ? " graphs=off" : " graphs=on") +
                               (p->kernel == GS_KERNEL_EULER

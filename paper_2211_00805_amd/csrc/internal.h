@@ -96,6 +96,7 @@ struct StepArgs {
     int32_t flags;
     int32_t cmask;        // terms added to the accumulator: 1 T_{k-2}, 2 T_{k-1}, 4 T_k
     int32_t remap;        // 1: give each XCD a contiguous range of row tiles
+    int32_t csr_nt;       // 1: CSR loads with non-temporal hints; 0: cached
     int32_t long_thr;     // rows with more nonzeros go to the long-row blocks (0: none)
     int32_t nlong;        // number of such rows
     const int32_t* long_rows;
@@ -111,12 +112,13 @@ struct StepArgs {
 };
 
 struct LaunchShape {
-    int vec;        // 1 (float) or 4 (float4)
-    int S;          // lanes splitting a row's nonzeros
-    int C;          // lanes over column groups of `vec` floats
-    int remap = 1;  // XCD-contiguous block order
+    int vec;         // 1 (float) or 4 (float4)
+    int S;           // lanes splitting a row's nonzeros
+    int C;           // lanes over column groups of `vec` floats
+    int remap = 1;   // XCD-contiguous block order
+    int csr_nt = 1;  // CSR read with non-temporal hints (streamed) or cached (graphs that fit the caches)
     bool operator==(const LaunchShape& o) const {
-        return vec == o.vec && S == o.S && C == o.C && remap == o.remap;
+        return vec == o.vec && S == o.S && C == o.C && remap == o.remap && csr_nt == o.csr_nt;
     }
 };
 

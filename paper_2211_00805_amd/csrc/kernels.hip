@@ -262,8 +262,8 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
         for (int u = 0; u < kUnroll; ++u) {
             const int eu = e + u * SL;
             const bool ok = eu < re;
-            const int j = ok ? __builtin_nontemporal_load(A.col + eu) : row;
-            w[u] = ok ? __builtin_nontemporal_load(A.val + eu) : 0.f;
+            const int j = ok ? (A.csr_nt ? __builtin_nontemporal_load(A.col + eu) : A.col[eu]) : row;
+            w[u] = ok ? (A.csr_nt ? __builtin_nontemporal_load(A.val + eu) : A.val[eu]) : 0.f;
             xv[u] = vload<VEC>(xcol + (size_t)j * A.ldp);
         }
 #pragma unroll
@@ -349,9 +349,14 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int self = valid ? row : r0;
     for (int cb = eb; cb < ee; cb += kChunk) {
         const int cend = cb + kChunk < ee ? cb + kChunk : ee;
-        for (int e = cb + (int)threadIdx.x; e < cend; e += kBlock)
-            stage[e - cb] = make_int2(__builtin_nontemporal_load(A.col + e),
-                                      __float_as_int(__builtin_nontemporal_load(A.val + e)));
+        if (A.csr_nt) {   // streamed CSR: keep L2 for the gathered rows
+            for (int e = cb + (int)threadIdx.x; e < cend; e += kBlock)
+                stage[e - cb] = make_int2(__builtin_nontemporal_load(A.col + e),
+                                          __float_as_int(__builtin_nontemporal_load(A.val + e)));
+        } else {          // a CSR that fits the caches stays there across steps
+            for (int e = cb + (int)threadIdx.x; e < cend; e += kBlock)
+                stage[e - cb] = make_int2(A.col[e], __float_as_int(A.val[e]));
+        }
         __syncthreads();
         const int lo = rs > cb ? rs : cb;
         const int hi = re < cend ? re : cend;
@@ -675,19 +680,20 @@ int long_row_threshold(const LaunchShape& s) {
 
 std::vector<LaunchShape> candidate_shapes(int ldp) {
     std::vector<LaunchShape> out;
-    for (int remap : {1, 0}) {
-        if (ldp == 1) {
-            for (int S : {2, 4, 8, 16, 32, 64}) out.push_back({1, S, 1, remap});
-            continue;
-        }
-        for (int C : {1, 2, 4, 8, 16, 32, 64}) {
-            if (!column_lanes_ok(ldp, 4, C)) continue;
-            for (int S : {1, 2, 4, 8, 16}) {
-                LaunchShape s{4, S, C, remap};
-                if (shape_supported(s)) out.push_back(s);
+    for (int nt : {1, 0})
+        for (int remap : {1, 0}) {
+            if (ldp == 1) {
+                for (int S : {2, 4, 8, 16, 32, 64}) out.push_back({1, S, 1, remap, nt});
+                continue;
+            }
+            for (int C : {1, 2, 4, 8, 16, 32, 64}) {
+                if (!column_lanes_ok(ldp, 4, C)) continue;
+                for (int S : {1, 2, 4, 8, 16}) {
+                    LaunchShape s{4, S, C, remap, nt};
+                    if (shape_supported(s)) out.push_back(s);
+                }
             }
         }
-    }
     return out;
 }
 
@@ -700,6 +706,7 @@ std::vector<LaunchShape> candidate_shapes(int ldp) {
 void launch_step(const LaunchShape& shape, const StepArgs& a_in, hipStream_t st) {
     StepArgs a = a_in;
     a.remap = shape.remap;
+    a.csr_nt = shape.csr_nt;
     GS_SHAPE_CASE(1, 2, 1) GS_SHAPE_CASE(1, 4, 1) GS_SHAPE_CASE(1, 8, 1) GS_SHAPE_CASE(1, 16, 1)
     GS_SHAPE_CASE(1, 32, 1) GS_SHAPE_CASE(1, 64, 1)
     GS_SHAPE_CASE(4, 1, 1) GS_SHAPE_CASE(4, 2, 1) GS_SHAPE_CASE(4, 4, 1) GS_SHAPE_CASE(4, 8, 1) GS_SHAPE_CASE(4, 16, 1)

@@ -203,11 +203,11 @@ double tridiag_last_component(const std::vector<double>& al, const std::vector<d
 // (at most 16; a short last tile or idle lanes when the groups are not a
 // power of two), and S = 8 / C lanes over a row's nonzeros.
 LaunchShape default_shape(int ldp, double nnz_per_row) {
-    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1};
+    if (ldp == 1) return {1, nnz_per_row > 12.0 ? 16 : 8, 1, 1, 1};
     int C = 1;
     while (C < 16 && C < ldp / 4) C *= 2;
     int S = std::max(1, 8 / C);
-    return {4, S, C, 1};
+    return {4, S, C, 1, 1};
 }
 
 }  // namespace gs
@@ -523,10 +523,12 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
         std::map<std::string, std::string> cache;
         if (tune_cache) cache = read_cache(tune_cache);
         const auto hit = cache.find(key);
-        int vv = 0, ss = 0, cc = 0, rr = 1;
-        if (hit != cache.end() && std::sscanf(hit->second.c_str(), "%d,%d,%d,%d", &vv, &ss, &cc, &rr) == 4 &&
-            shape_supported({vv, ss, cc, rr}) && column_lanes_ok(P->ldp, vv, cc) && (vv == 1) == (P->ldp == 1)) {
-            P->shape = {vv, ss, cc, rr};
+        int vv = 0, ss = 0, cc = 0, rr = 1, nt = 1;   // entries without the fifth field: streamed CSR
+        const int got = hit != cache.end()
+                            ? std::sscanf(hit->second.c_str(), "%d,%d,%d,%d,%d", &vv, &ss, &cc, &rr, &nt) : 0;
+        if (got >= 4 && shape_supported({vv, ss, cc, rr, nt}) && column_lanes_ok(P->ldp, vv, cc) &&
+            (vv == 1) == (P->ldp == 1) && (nt == 0 || nt == 1)) {
+            P->shape = {vv, ss, cc, rr, nt};
             P->shape_origin = "cache";
         } else {
             hipStream_t st = P->cap;
@@ -546,7 +548,8 @@ gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cac
             P->shape_origin = "autotuned";
             if (tune_cache) {
                 cache[key] = std::to_string(P->shape.vec) + "," + std::to_string(P->shape.S) + "," +
-                             std::to_string(P->shape.C) + "," + std::to_string(P->shape.remap);
+                             std::to_string(P->shape.C) + "," + std::to_string(P->shape.remap) + "," +
+                             std::to_string(P->shape.csr_nt);
                 write_cache(tune_cache, cache);
             }
         }

@@ -2,11 +2,12 @@
 
 Barycenter: ||p_gpu - p_ref||_1 <= 1e-6.  Gradients: ||g - g_ref||_2 /
 ||g_ref||_2 <= 1e-4 on the supports, and sampled coordinates within 1e-4 of
-max(|g_ref_i|, 1e-2 ||g_ref||_inf); the t-gradient within 1e-4 relative.
+max(|g_ref_i|, 1e-3 ||g_ref||_inf); the t-gradient within 1e-4 relative.
 The per-coordinate floor: float32 gradient entries carry an absolute error
 of a few u * ||g||_inf (u = 2^-24, entries are sums of 4t ln v terms of size
-up to ||g||_inf), so a coordinate that cancels to ~1e-3 ||g||_inf cannot be
-accurate to 1e-4 of itself; 1e-4 * 1e-2 ||g||_inf = 1e-6 ||g||_inf is ~17 u.
+up to ||g||_inf), so a coordinate that cancels to near zero cannot be
+accurate to 1e-4 of itself; 1e-4 * 1e-3 ||g||_inf = 1e-7 ||g||_inf is ~1.7 u.
+The tests print the worst ratio with both the 1e-3 floor and a 1e-2 floor.
 """
 import numpy as np
 import pytest
@@ -209,6 +210,7 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
     gmu = torch.empty(n * B, device="cuda")
     gnu = torch.empty(n * B, device="cuda")
     gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, gd, grad_mu=gmu, grad_nu=gnu)
+    worst = {1e-3: 0.0, 1e-2: 0.0}
     for got, want, h in ((to_host(gmu).reshape(n, B), ref["dmu"], mu), (to_host(gnu).reshape(n, B), ref["dnu"], nu)):
         for b in range(B):
             s = h[:, b] > 0
@@ -216,8 +218,13 @@ def test_backward_matches_oracle_reverse_mode(gs, clusters, J, ce):
             rel = np.linalg.norm(got[s, b] - want[s, b]) / np.linalg.norm(want[s, b])
             assert rel <= 1e-4, (b, rel)
             idx = np.nonzero(s)[0][:: max(1, s.sum() // 16)][:16]
-            scale = np.maximum(np.abs(want[idx, b]), 1e-2 * np.abs(want[s, b]).max())
-            assert np.all(np.abs(got[idx, b] - want[idx, b]) <= 1e-4 * scale)
+            for fl in worst:
+                scale = np.maximum(np.abs(want[idx, b]), fl * np.abs(want[s, b]).max())
+                worst[fl] = max(worst[fl], float(np.max(np.abs(got[idx, b] - want[idx, b]) / scale)))
+    # sampled coordinates: |g - g_ref| / max(|g_ref,i|, floor ||g_ref||_inf), both floors reported
+    print(f"J={J} ce={ce}: worst sampled-coordinate error / max(|g_i|, 1e-3 ||g||_inf) = {worst[1e-3]:.2e}, "
+          f"with 1e-2 ||g||_inf = {worst[1e-2]:.2e}")
+    assert worst[1e-3] <= 1e-4
     np.testing.assert_allclose(gt, ref["dt"], rtol=1e-4)
 
 
@@ -276,8 +283,11 @@ def test_gradient_matches_fp64_finite_differences(gs, clusters):
     gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, gs.GS_RECORD_ALL, rec, [1.0], grad_mu=gmu)
     got = to_host(gmu)[coords]
     full = osk.sinkhorn_grad(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J)["dmu"][:, 0]
-    scale = np.maximum(np.abs(fd), 1e-2 * np.abs(full[m64 > 0]).max())
-    assert np.all(np.abs(got - fd) <= 1e-4 * scale), np.abs(got - fd) / scale
+    ratios = {fl: float(np.max(np.abs(got - fd) / np.maximum(np.abs(fd), fl * np.abs(full[m64 > 0]).max())))
+              for fl in (1e-3, 1e-2)}
+    print(f"worst coordinate error against central differences / max(|fd_i|, floor ||g||_inf): "
+          f"1e-3 floor {ratios[1e-3]:.2e}, 1e-2 floor {ratios[1e-2]:.2e}")
+    assert ratios[1e-3] <= 1e-4, ratios
     assert gt[0] == pytest.approx(fdt[0], rel=1e-4)
 
 

@@ -168,9 +168,14 @@ def test_heat_apply_every_launch_shape(gs, swiss, B):
     Y = torch.empty(n * B, device="cuda")
     for shape in _shapes(B):
         plan.set_shape(*shape)
-        gs.gs_heat_apply(plan, lam, t, xd, Y)
-        err = np.abs(to_host(Y).reshape(n, B) - ref).max()
-        assert err <= heat_tol(K, np.abs(x).max()), (shape, err)
+        outs = []
+        for streamed in (True, False):   # CSR loads non-temporal or cached: bitwise the same
+            plan.set_csr_hint(streamed)
+            gs.gs_heat_apply(plan, lam, t, xd, Y)
+            outs.append(to_host(Y).reshape(n, B))
+            err = np.abs(outs[-1] - ref).max()
+            assert err <= heat_tol(K, np.abs(x).max()), (shape, streamed, err)
+        assert np.array_equal(outs[0], outs[1]), shape
 
 
 @pytest.mark.parametrize("B", [1, 10, 32])
@@ -189,6 +194,7 @@ def test_heat_apply_rows_of_very_high_degree(gs, B):
         Y = torch.empty(n * B, device="cuda")
         for shape in _shapes(B):
             plan.set_shape(*shape)
+            plan.set_csr_hint(shape[1] % 2 == 0)   # hub rows through both CSR load forms
             gs.gs_heat_apply(plan, lam, t, to_dev(x), Y)
             err = np.abs(to_host(Y).reshape(n, B) - ref).max()
             assert err <= heat_tol(K, np.abs(x).max()), (shape, err)

@@ -117,7 +117,7 @@ def test_concurrent_autotuning_leaves_a_valid_cache(gs, tmp_path):
     assert 1 <= len(entries) <= 2
     for key, val in entries.items():
         assert key.endswith(":B=4") or key.endswith(":B=16")
-        assert len(val.split(",")) == 4
+        assert len(val.split(",")) == 5   # vec, S, C, XCD order, CSR hint
     assert not [p for p in tmp_path.iterdir() if ".tmp." in p.name]
     for key in entries:
         B = int(key.split("B=")[1])
