@@ -1,0 +1,306 @@
+"""GPU parity at each workload's own size and iteration count against stored float64 oracle values.
+
+The expected values come from `tests/golden/make_fullsize.py`, which calls only
+the oracle and the seeded input generators (run once on a CPU; the float64
+runs take from minutes to an hour each).  Each test rebuilds the same inputs,
+checks their digests against the stored ones, runs the library through the
+C ABI in the autotuned launch the benchmark uses, and compares:
+
+  * distances: |dD| <= 1e-5 max(|D_ref|, 4t) (Algorithm 1's return value);
+  * plans: the row marginal a v p_K(a w) of the GPU's (v, w), evaluated with
+    the oracle's float64 operator, against the oracle's own, within 1e-6 L1;
+  * barycenters: ||p - p_ref||_1 <= 1e-6;
+  * gradients: ||g - g_ref||_2 / ||g_ref||_2 <= 1e-4 on the supports, sampled
+    coordinates against central differences, d/dt within 1e-4 relative.
+
+Graphs: the library builds the kNN graph from the points; its structure must
+equal the oracle's bit for bit (digests of rowptr and col), and the parity runs
+use the oracle's Gaussian weights of that structure (digest checked), so both
+sides consume the same float32 inputs.  lambda_hat = 1.01 lambda_max from the
+oracle is given to both sides, and the library's own estimate is checked to
+lie between lambda_max and the edge bound.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import graph as ograph
+from oracle import sinkhorn as osk
+from gpu_common import need_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, f"fullsize_{name}.json")) as f:
+        rec = json.load(f)
+    arr = dict(np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz")))
+    return rec, arr
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2211_00805_amd as g
+    return g
+
+
+def dist_ok(D, Dref, t):
+    return abs(D - Dref) <= 1e-5 * max(abs(Dref), 4 * t)
+
+
+def oracle_weights(X, rp, col, median):
+    """The oracle's Gaussian weights of a given structure (float32), in chunks of edges."""
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    out = np.empty(col.shape[0], dtype=np.float32)
+    step = 1 << 20
+    for e0 in range(0, col.shape[0], step):
+        e1 = min(col.shape[0], e0 + step)
+        out[e0:e1] = ograph.gaussian_weights(X, rows[e0:e1], col[e0:e1].astype(np.int64), median).astype(np.float32)
+    return out
+
+
+def ulp_diff(a, b):
+    ia = a.view(np.int32).astype(np.int64)
+    ib = b.view(np.int32).astype(np.int64)
+    return np.abs(ia - ib)
+
+
+def checked_graph(gs, X, grec):
+    """Library kNN build (structure checked) re-created with the oracle's weights; the float64 Laplacian."""
+    g0 = gs.gs_graph_from_points(X, grec["k"])
+    rp, col, w_lib, _ = g0.export()
+    assert synth.sha256(rp) == grec["rowptr_sha256"], "kNN graph structure (rowptr) differs from the oracle's"
+    assert synth.sha256(col) == grec["col_sha256"], "kNN graph structure (col) differs from the oracle's"
+    w = oracle_weights(X, rp, col, grec["median"])
+    assert synth.sha256(w) == grec["w_sha256"], "oracle weights recomputed here differ from the stored ones"
+    assert ulp_diff(w_lib, w).max() <= 2, "library weights more than 2 ulp from the oracle's"
+    g0.destroy()
+    g = gs.gs_graph_from_csr(grec["n"], rp, col, w)
+    L = ograph.laplacian(ograph.csr_from_arrays(grec["n"], rp, col, w.astype(np.float64)))
+    return g, L
+
+
+def check_lambda(gs, g, grec, seed):
+    lam_lib = gs.gs_lambda_max(g, iters=60, seed=seed, safety=1.01)
+    print(f"lambda_max {grec['lambda_max']:.6f}  library lambda_hat {lam_lib:.6f}  edge bound {grec['edge_bound']:.6f}")
+    assert grec["lambda_max"] * (1 + 1e-9) <= lam_lib <= grec["edge_bound"] * (1 + 1e-6)
+
+
+def support_l1(got_full, ref_on_supp, supp):
+    """L1 distance of a full-length vector from one stored on `supp` (zero elsewhere)."""
+    off = np.ones(got_full.shape[0], dtype=bool)
+    off[supp] = False
+    return float(np.abs(got_full[supp] - ref_on_supp.astype(np.float64)).sum() + np.abs(got_full[off]).sum())
+
+
+# ----------------------------------------------------------------------------- 100k plain forward
+
+def test_curve_100k_three_times(gs):
+    """n = 100k cluster curve, one pair, K = 30, J = 500, t in {0.5, 2, 8} (the plain forward workload),
+    through the accumulating and the Clenshaw step forms."""
+    rec, arr = load("curve")
+    X, labels, mu, nu = synth.curve_pair_workload()
+    assert synth.sha256(X) == rec["points_sha256"] and synth.sha256(mu) == rec["mu_sha256"]
+    assert synth.sha256(nu) == rec["nu_sha256"]
+    grec = rec["graph"]
+    g, L = checked_graph(gs, X, grec)
+    check_lambda(gs, g, grec, seed=2)
+    lam, K, J, n = grec["lambda_hat"], rec["K"], rec["J"], grec["n"]
+    plan = gs.Plan(g, K, 1, flags=gs.GS_PLAN_AUTOTUNE)
+    supp = np.nonzero(mu > 0)[0]
+    v = torch.empty(n, device="cuda")
+    w = torch.empty(n, device="cuda")
+    for kernel in (gs.GS_KERNEL_CHEBYSHEV, gs.GS_KERNEL_CLENSHAW):   # the same polynomial, two recurrences
+        plan.set_kernel(kernel)
+        for run in rec["runs"]:
+            t = run["t"]
+            out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, v=v, w=w, want_marg=True,
+                                 want_floors=True)
+            D = float(out["dist"][0])
+            r = osk.row_marginal(L, lam, t, K, to_host(v), to_host(w))[:, 0]
+            l1 = support_l1(r, arr[f"row_t{t}"], supp)
+            print(f"t={t}: D {D:.9f} oracle {run['D']:.9f} (rel {abs(D - run['D']) / abs(run['D']):.1e}); "
+                  f"plan L1 {l1:.2e}; floors {out['n_floored']} / {run['n_floored']}; plan {plan.describe()}")
+            assert dist_ok(D, run["D"], t), (t, D, run["D"])
+            assert l1 <= 1e-6, (t, l1)
+            assert out["n_floored"] == run["n_floored"]
+
+
+# ----------------------------------------------------------------------------- 200k barycenter and its 20k twin
+
+@pytest.mark.parametrize("which", ["full", "twin"])
+def test_barycenter_200k_and_20k_twin(gs, which):
+    """m = 64, K = 40, t = 2: 20 iterations at n = 200k, all 300 at n = 20k (same recipe)."""
+    rec, arr = load("bary")
+    if which == "full":
+        X, _, H = synth.barycenter_workload()
+        grec, psha, hsha = rec["graph"], rec["points_sha256"], rec["H_sha256"]
+    else:
+        X, _, H = synth.barycenter_workload(667, 100, 5000)
+        grec, psha, hsha = rec["twin_graph"], rec["twin_points_sha256"], rec["twin_H_sha256"]
+    assert synth.sha256(X) == psha and synth.sha256(H) == hsha
+    g, L = checked_graph(gs, X, grec)
+    check_lambda(gs, g, grec, seed=3)
+    run = rec[which]
+    lam, K, t, J, m, n = grec["lambda_hat"], rec["K"], rec["t"], run["J"], rec["m"], grec["n"]
+    plan = gs.Plan(g, K, m, flags=gs.GS_PLAN_AUTOTUNE)
+    bary = torch.empty(n, device="cuda")
+    out = gs.gs_barycenter(plan, lam, t, to_dev(H), np.full(m, 1.0 / m), J, bary, want_marg=True, want_floors=True)
+    p = to_host(bary)
+    l1 = float(np.abs(p - arr[f"p_{which}"].astype(np.float64)).sum())
+    # each side's own marginal violation (convergence, not parity): equal to a percent
+    dm = np.abs(out["marg_err"] - np.asarray(run["marg_row"])) / np.maximum(np.asarray(run["marg_row"]), 1e-5)
+    print(f"{which}: n={n} J={J} barycenter L1 {l1:.2e} (mass {p.sum():.9f} oracle {run['mass']:.9f}); "
+          f"per-input marginal errors differ by <= {dm.max():.1e} relative; floors {out['n_floored']} / {run['n_floored']}; "
+          f"plan {plan.describe()}")
+    assert l1 <= 1e-6, l1
+    assert out["n_floored"] == run["n_floored"]
+    assert np.all(dm <= 1e-2), dm.max()
+
+
+# ----------------------------------------------------------------------------- 200k gradients
+
+@pytest.fixture(scope="module")
+def grad_setup(gs):
+    rec, arr = load("grad")
+    X, labels, _ = synth.barycenter_workload()
+    mu, nu = synth.gradient_pairs(labels)
+    assert synth.sha256(X) == rec["points_sha256"]
+    assert synth.sha256(mu) == rec["mu_sha256"] and synth.sha256(nu) == rec["nu_sha256"]
+    g, L = checked_graph(gs, X, rec["graph"])
+    return rec, arr, mu, nu, g, L
+
+
+@pytest.mark.parametrize("form", ["ckpt10", "records"])
+def test_gradients_200k_32_pairs(gs, grad_setup, form):
+    """32 pairs, K = 30, t = 2, J = 200; checkpoints every 10 iterations (the workload's form) or records."""
+    rec, arr, mu, nu, g, L = grad_setup
+    grec = rec["graph"]
+    lam, K, t, J, n = grec["lambda_hat"], rec["K"], rec["t"], rec["J"], grec["n"]
+    B = mu.shape[1]
+    plan = gs.Plan(g, K, B, flags=gs.GS_PLAN_AUTOTUNE)
+    ce = 10 if form == "ckpt10" else gs.GS_RECORD_ALL
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    v = torch.empty(n * B, device="cuda")
+    w = torch.empty(n * B, device="cuda")
+    mud, nud = to_dev(mu), to_dev(nu)
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=ce, ckpt=ckpt, v=v, w=w, want_floors=True)
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, np.ones(B), grad_mu=gmu, grad_nu=gnu)
+    V = to_host(v).reshape(n, B)
+    W = to_host(w).reshape(n, B)
+    GM = to_host(gmu).reshape(n, B)
+    GN = to_host(gnu).reshape(n, B)
+    refs = rec["ref_pairs"]
+    row = osk.row_marginal(L, lam, t, K, V[:, refs], W[:, refs])
+    fd_by_pair = {}
+    for r in rec["fd_mu"]:
+        fd_by_pair.setdefault(r["pair"], []).append(r)
+    worst = {"D": 0.0, "plan": 0.0, "l2": 0.0, "coord": 0.0, "coord_fd": 0.0, "t": 0.0, "t_fd": 0.0}
+    for q, c in enumerate(refs):
+        ref = rec[f"ref_{c}"]
+        sm, sn = np.nonzero(mu[:, c] > 0)[0], np.nonzero(nu[:, c] > 0)[0]
+        assert dist_ok(float(out["dist"][c]), ref["D"], t), (c, out["dist"][c], ref["D"])
+        worst["D"] = max(worst["D"], abs(out["dist"][c] - ref["D"]) / max(abs(ref["D"]), 4 * t))
+        l1 = support_l1(row[:, q], arr[f"row_{c}"], sm)
+        worst["plan"] = max(worst["plan"], l1)
+        g_ref = np.concatenate([arr[f"dmu_{c}"], arr[f"dnu_{c}"]]).astype(np.float64)
+        g_got = np.concatenate([GM[sm, c], GN[sn, c]])
+        rel = np.linalg.norm(g_got - g_ref) / np.linalg.norm(g_ref)
+        worst["l2"] = max(worst["l2"], rel)
+        ginf = np.abs(g_ref).max()
+        for r in fd_by_pair[c]:
+            got = GM[r["node"], c]
+            worst["coord"] = max(worst["coord"], abs(got - r["ref"]) / max(abs(r["ref"]), 1e-3 * ginf))
+            worst["coord_fd"] = max(worst["coord_fd"], abs(got - r["fd"]) / max(abs(r["fd"]), 1e-3 * ginf))
+        worst["t"] = max(worst["t"], abs(gt[c] - ref["dt"]) / abs(ref["dt"]))
+        worst["t_fd"] = max(worst["t_fd"], abs(gt[c] - rec[f"fd_t_{c}"]) / abs(rec[f"fd_t_{c}"]))
+        assert out["n_floored"] >= 0
+    print(f"{form}: worst over pairs {refs}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items())
+          + f"; float64 reference vs differences {rec['ref_vs_fd_max_rel']}; plan {plan.describe()}")
+    assert worst["plan"] <= 1e-6
+    assert worst["l2"] <= 1e-4
+    # sampled coordinates: 1e-4 of max(|g_i|, 1e-3 ||g||_inf), against the reference and the differences
+    assert worst["coord"] <= 1e-4 and worst["coord_fd"] <= 1e-4
+    assert worst["t"] <= 1e-4 and worst["t_fd"] <= 1e-4
+
+
+def test_gradient_forms_agree_bitwise_200k(gs, grad_setup):
+    """Checkpoints every 10 iterations and records give bitwise the same gradients at full size."""
+    rec, arr, mu, nu, g, L = grad_setup
+    grec = rec["graph"]
+    lam, K, t, J, n = grec["lambda_hat"], rec["K"], rec["t"], rec["J"], grec["n"]
+    B = mu.shape[1]
+    plan = gs.Plan(g, K, B, flags=gs.GS_PLAN_AUTOTUNE)
+    mud, nud = to_dev(mu), to_dev(nu)
+    res = []
+    for ce in (10, gs.GS_RECORD_ALL):
+        ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+        gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=ce, ckpt=ckpt)
+        gmu = torch.empty(n * B, device="cuda")
+        gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, np.ones(B), grad_mu=gmu)
+        res.append((gmu.cpu().numpy(), gt))
+        del ckpt
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+# ----------------------------------------------------------------------------- 1M local graph, fwd + bwd
+
+def test_local_graph_1m_forward_backward(gs):
+    """n = 1M random local graph (18.4M nonzeros, hub rows), 32 pairs, K = 50, t = 2, J = 200, records."""
+    rec, arr = load("local1m")
+    grec = rec["graph"]
+    rp, col, w = synth.local_graph_1m()
+    n = rp.shape[0] - 1
+    assert synth.sha256(rp) == grec["rowptr_sha256"] and synth.sha256(col) == grec["col_sha256"]
+    assert synth.sha256(w) == grec["w_sha256"]
+    mu, nu = synth.loguniform_pair_batch(n, 32, 5000, 200000, 10)
+    assert synth.sha256(mu) == rec["mu_sha256"] and synth.sha256(nu) == rec["nu_sha256"]
+    g = gs.gs_graph_from_csr(n, rp, col, w)
+    check_lambda(gs, g, grec, seed=10)
+    L = ograph.laplacian(ograph.csr_from_arrays(n, rp, col, w.astype(np.float64)))
+    del rp, col, w
+    lam, K, t, J = grec["lambda_hat"], rec["K"], rec["t"], rec["J"]
+    B = mu.shape[1]
+    plan = gs.Plan(g, K, B, flags=gs.GS_PLAN_AUTOTUNE)
+    ce = gs.GS_RECORD_ALL
+    ckpt = torch.empty(gs.ckpt_floats(plan, J, ce), device="cuda")
+    v = torch.empty(n * B, device="cuda")
+    w_ = torch.empty(n * B, device="cuda")
+    mud, nud = to_dev(mu), to_dev(nu)
+    out = gs.gs_sinkhorn(plan, lam, t, mud, nud, J, ckpt_every=ce, ckpt=ckpt, v=v, w=w_)
+    gmu = torch.empty(n * B, device="cuda")
+    gnu = torch.empty(n * B, device="cuda")
+    gt = gs.gs_sinkhorn_backward(plan, lam, t, mud, nud, J, ce, ckpt, np.ones(B), grad_mu=gmu, grad_nu=gnu)
+    del ckpt
+    refs = rec["ref_pairs"]
+    V = to_host(v).reshape(n, B)[:, refs]
+    W = to_host(w_).reshape(n, B)[:, refs]
+    row = osk.row_marginal(L, lam, t, K, V, W)
+    GM = to_host(gmu).reshape(n, B)
+    GN = to_host(gnu).reshape(n, B)
+    for q, c in enumerate(refs):
+        ref = rec[f"ref_{c}"]
+        sm, sn = np.nonzero(mu[:, c] > 0)[0], np.nonzero(nu[:, c] > 0)[0]
+        D = float(out["dist"][c])
+        l1 = support_l1(row[:, q], arr[f"row_{c}"], sm)
+        g_ref = np.concatenate([arr[f"dmu_{c}"], arr[f"dnu_{c}"]]).astype(np.float64)
+        g_got = np.concatenate([GM[sm, c], GN[sn, c]])
+        rel = np.linalg.norm(g_got - g_ref) / np.linalg.norm(g_ref)
+        trel = abs(gt[c] - ref["dt"]) / abs(ref["dt"])
+        print(f"pair {c}: D {D:.9f} oracle {ref['D']:.9f}; plan L1 {l1:.2e}; gradient L2 rel {rel:.2e}; "
+              f"d/dt rel {trel:.2e}; plan {plan.describe()}")
+        assert dist_ok(D, ref["D"], t)
+        assert l1 <= 1e-6
+        assert rel <= 1e-4
+        assert trel <= 1e-4
