@@ -65,21 +65,33 @@ def test_gradient_fixture_against_central_differences():
     A central difference with step h carries the rounding error of D divided
     by h: D (about 60-110 here) comes out of J = 200 float64 iterations
     accurate to a few tens of ulp, so at the workload's relative step 1e-4 on
-    small weights (h down to 6e-10) that term reaches 1e-5 relative.  Checked:
-    every coordinate within 1e-6 relative plus 128 ulp of D over 2h; with the
-    relative step 1e-3, where that term is ten times smaller and truncation
-    stays near 1e-8, within 1e-6 relative outright; d/dt within 1e-6.
+    small weights (h down to 6e-10) that term reaches 1e-5 relative.  Checked,
+    at both relative steps (1e-4, the workload's, and 1e-3, where that term is
+    ten times smaller and truncation stays near 1e-8): every coordinate within
+    1e-6 relative plus 128 ulp of D over 2h; at the step 1e-3, every
+    coordinate whose rounding term is below 1e-6 relative within 1e-6
+    relative outright; the agreement improves with the larger step (the
+    differences' rounding, not the reference, sets it); d/dt within 1e-6.
     """
     rec, arr = load("grad")
     graph_ok(rec["graph"])
     assert rec["ref_vs_fd_max_rel"]["t"] <= 1e-6
     assert len(rec["fd_mu"]) == 16 and {r["pair"] for r in rec["fd_mu"]} == {0, 1, 2, 3}
     eps = np.finfo(np.float64).eps
+    pinned, err4, err3 = 0, [], []
     for r in rec["fd_mu"]:
         D = rec[f"ref_{r['pair']}"]["D"]
         assert abs(r["ref"] - r["fd"]) <= 1e-6 * abs(r["fd"]) + 128 * eps * abs(D) / (2 * r["h"]), r
-        if "fd_rel1e-3" in r:
-            assert abs(r["ref"] - r["fd_rel1e-3"]) <= 1e-6 * abs(r["fd_rel1e-3"]), r
+        err4.append(abs(r["ref"] - r["fd"]) / abs(r["fd"]))
+        fd3, h3 = r["fd_rel1e-3"], r["h_rel1e-3"]
+        rounding3 = 128 * eps * abs(D) / (2 * h3)
+        assert abs(r["ref"] - fd3) <= 1e-6 * abs(fd3) + rounding3, r
+        err3.append(abs(r["ref"] - fd3) / abs(fd3))
+        if rounding3 < 1e-6 * abs(fd3):
+            assert abs(r["ref"] - fd3) <= 1e-6 * abs(fd3), r
+            pinned += 1
+    assert pinned >= 12
+    assert np.median(err3) < np.median(err4) / 3
     for c in rec["ref_pairs"]:
         ref = rec[f"ref_{c}"]
         assert ref["D"] == pytest.approx(ref["D_grad_run"], rel=1e-12)
