@@ -202,3 +202,29 @@ def test_clenshaw_one_million_nodes_sampled_columns(gs):
     ref = heat.heat_apply(L, lam, t, K, x[:, cols].astype(np.float64))
     err = np.abs(to_host(Y).reshape(n, B)[:, cols] - ref).max()
     assert err <= heat_tol(K, np.abs(x).max()), (err, plan.describe())
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_clenshaw_sinkhorn_smallest_degrees_with_vertex_weights(gs, K):
+    """Algorithm 1 with vertex weights through the Clenshaw kernel at K = 1, 2, 3,
+    where the first and last products coincide or touch (the scaling epilogue
+    on product 1, the folded u_K term on the last): distances and plans."""
+    X = synth.swiss_roll(2000, 10, 0.05, workload=1)
+    arrs, L, info, A = oracle_csr(X, 10)
+    n, t, J, B = 2000, 1.0, 30, 4
+    rng = np.random.default_rng(40 + K)
+    mu = np.stack([synth.uniform_on_random_nodes(n, 300, rng) for _ in range(B)], axis=1)
+    nu = np.stack([synth.uniform_on_random_nodes(n, 300, rng) for _ in range(B)], axis=1)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    lam = lam_hat_of(L)
+    ref = osk.sinkhorn(L, lam, t, K, mu.astype(np.float64), nu.astype(np.float64), J, a=a.astype(np.float64))
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = clen_plan(gs, g, K, B)
+    v = torch.empty(n * B, device="cuda")
+    w = torch.empty(n * B, device="cuda")
+    out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, a=to_dev(a), v=v, w=w, want_floors=True)
+    assert out["n_floored"] == ref["n_floored"]
+    assert np.all(np.abs(out["dist"] - ref["D"]) <= 1e-5 * np.maximum(np.abs(ref["D"]), 4 * t)), (out["dist"], ref["D"])
+    r = osk.row_marginal(L, lam, t, K, to_host(v).reshape(n, B), to_host(w).reshape(n, B), a.astype(np.float64))
+    rr = osk.row_marginal(L, lam, t, K, ref["v"], ref["w"], a.astype(np.float64))
+    assert np.abs(r - rr).sum(axis=0).max() <= 1e-6
