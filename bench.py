@@ -152,13 +152,73 @@ def cpu_baseline(rp, col, w, K: int, t: float, lam: float, mu, nu, csr_sha: str)
     dt = time.perf_counter() - t0
     applies = 1 * (2 * J + 2 * J)
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    parallel = cpu_rhs_parallel(rp, col, w, K, t, lam, min(16, ncores))
     return {"value": applies / dt, "unit": "heat-kernel applies/s", "cores": 1, "kind": "oracle",
             "sample": (f"float64 oracle (scipy CSR products, single thread; host affinity {ncores} cores, "
                        f"os.cpu_count() {os.cpu_count()}) on the workload's own graph (exported CSR sha256 "
                        f"{csr_sha[:16]}, n={n}, nnz={col.shape[0]}, same lambda_hat): 1 Sinkhorn iteration "
                        f"forward + reverse sweep for 1 pair of the first batch, K={K}, t={t}; {applies} applies "
                        f"in {dt:.1f} s"),
-            "single_applies": single}
+            "single_applies": single, "rhs_parallel": parallel}
+
+
+_RHS_CHILD = r"""
+import os, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import graph as ograph
+from oracle import heat
+d, i, K, t, lam = sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), float(sys.argv[5]), float(sys.argv[6])
+rp, col, w = (np.load(os.path.join(d, f + ".npy")) for f in ("rp", "col", "w"))
+L = ograph.laplacian(ograph.csr_from_arrays(rp.shape[0] - 1, rp, col, w.astype(np.float64)))
+x = np.random.default_rng(100 + i).uniform(0.05, 1.0, size=(rp.shape[0] - 1, 1))
+open(os.path.join(d, f"ready{i}"), "w").close()
+while not os.path.exists(os.path.join(d, "go")):
+    time.sleep(0.01)
+t0 = time.perf_counter()
+heat.heat_apply(L, lam, t, K, x)
+print(time.perf_counter() - t0, flush=True)
+"""
+
+
+def cpu_rhs_parallel(rp, col, w, K: int, t: float, lam: float, procs: int):
+    """The oracle's single-RHS heat application in `procs` processes at once (one per host core).
+
+    Each process (a fresh interpreter, one thread) loads the exported CSR,
+    builds the float64 Laplacian, waits for a common start, and times one
+    application at B = 1; throughput = processes / the slowest one's time.
+    """
+    import shutil
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    d = tempfile.mkdtemp(prefix="gs_cpu_", dir=base)
+    try:
+        for name, arr in (("rp", rp), ("col", col), ("w", w)):
+            np.save(os.path.join(d, name + ".npy"), arr)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        kids = [subprocess.Popen([sys.executable, "-c", _RHS_CHILD, ROOT, d, str(i), str(K), str(t), repr(lam)],
+                                 stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+                for i in range(procs)]
+        deadline = time.time() + 300
+        while (not all(os.path.exists(os.path.join(d, f"ready{i}")) for i in range(procs))
+               and time.time() < deadline and all(k.poll() is None for k in kids)):
+            time.sleep(0.05)
+        open(os.path.join(d, "go"), "w").close()
+        times = []
+        for k in kids:
+            out, err = k.communicate(timeout=600)
+            if k.returncode != 0:
+                raise RuntimeError(f"oracle worker failed: {err[-500:]}")
+            times.append(float(out.strip().splitlines()[-1]))
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    return {"processes": procs, "applies_per_s": round(procs / max(times), 3), "seconds_max": round(max(times), 2),
+            "seconds_min": round(min(times), 2),
+            "sample": f"{procs} processes (one thread each), one B = 1 application of K = {K} each, started together"}
 
 
 def roofline_on_other_graphs(gs, synth, np, torch, dev, K: int, B: int):
