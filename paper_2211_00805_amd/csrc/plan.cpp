@@ -48,7 +48,6 @@ StepArgs base_args(gs_plan_s& P) {
     return a;
 }
 
-
 // Run `body` on `st` directly, or capture it once into a hipGraph (on the
 // plan's private stream) and replay the graph on `st`.
 template <class F>

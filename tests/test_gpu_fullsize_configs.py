@@ -205,7 +205,7 @@ def test_gradients_200k_32_pairs(gs, grad_setup, form):
     fd_by_pair = {}
     for r in rec["fd_mu"]:
         fd_by_pair.setdefault(r["pair"], []).append(r)
-    worst = {"D": 0.0, "plan": 0.0, "l2": 0.0, "coord": 0.0, "coord_fd": 0.0, "t": 0.0, "t_fd": 0.0}
+    worst = {"D": 0.0, "plan": 0.0, "l2": 0.0, "coord": 0.0, "coord_fd": 0.0, "coord_fd3": 0.0, "t": 0.0, "t_fd": 0.0}
     for q, c in enumerate(refs):
         ref = rec[f"ref_{c}"]
         sm, sn = np.nonzero(mu[:, c] > 0)[0], np.nonzero(nu[:, c] > 0)[0]
@@ -222,6 +222,8 @@ def test_gradients_200k_32_pairs(gs, grad_setup, form):
             got = GM[r["node"], c]
             worst["coord"] = max(worst["coord"], abs(got - r["ref"]) / max(abs(r["ref"]), 1e-3 * ginf))
             worst["coord_fd"] = max(worst["coord_fd"], abs(got - r["fd"]) / max(abs(r["fd"]), 1e-3 * ginf))
+            fd3 = r["fd_rel1e-3"]   # central differences at relative step 1e-3 (less float64 rounding)
+            worst["coord_fd3"] = max(worst["coord_fd3"], abs(got - fd3) / max(abs(fd3), 1e-3 * ginf))
         worst["t"] = max(worst["t"], abs(gt[c] - ref["dt"]) / abs(ref["dt"]))
         worst["t_fd"] = max(worst["t_fd"], abs(gt[c] - rec[f"fd_t_{c}"]) / abs(rec[f"fd_t_{c}"]))
         assert out["n_floored"] >= 0
@@ -230,7 +232,7 @@ def test_gradients_200k_32_pairs(gs, grad_setup, form):
     assert worst["plan"] <= 1e-6
     assert worst["l2"] <= 1e-4
     # sampled coordinates: 1e-4 of max(|g_i|, 1e-3 ||g||_inf), against the reference and the differences
-    assert worst["coord"] <= 1e-4 and worst["coord_fd"] <= 1e-4
+    assert worst["coord"] <= 1e-4 and worst["coord_fd"] <= 1e-4 and worst["coord_fd3"] <= 1e-4
     assert worst["t"] <= 1e-4 and worst["t_fd"] <= 1e-4
 
 
