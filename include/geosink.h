@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 #define GS_MAX_K 256          /* largest Chebyshev degree a plan accepts */
 
 typedef enum {

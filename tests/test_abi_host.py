@@ -97,8 +97,12 @@ def test_validation_rejects_before_any_device_call():
     assert lib.gs_stream_gather(None, 10, None, 4, None, None) == -1
     assert lib.gs_accumulate_columns(None, 10, 4, None, 2, None, None) == -1
     assert b"NULL" in lib.gs_last_error()
+    assert lib.gs_plan_set_csr_hint(None, 1) == -1
+    assert b"plan is NULL" in lib.gs_last_error()
+    assert lib.gs_heat_apply_noalloc(None, 2.0, 1.0, 10, None, None, 4, None) == -1
+    assert b"graph is NULL" in lib.gs_last_error()
 
 
 def test_abi_version():
     from paper_2211_00805_amd import gs_abi_version
-    assert gs_abi_version() == 1
+    assert gs_abi_version() == 2
