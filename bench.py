@@ -583,7 +583,8 @@ def footprint_study(args):
 
 
 def frontier_study(args):
-    """Work a frontier-sparse step could skip, per workload (one JSON line).
+    """Work a frontier-sparse step could skip, per workload, and what the
+    frontier option gains on the GPU (one JSON line).
 
     T_k of an application is zero outside the k-hop neighbourhood N^k(S) of the
     applied vector's support S (the union over the B columns of a launch, since
@@ -591,7 +592,10 @@ def frontier_study(args):
     the rows outside N^k(S), at most.  Reported: the fraction of rows and of
     nonzeros (the gathers) inside N^k(S) for k = 0..4, and the largest share
     of an application's gathers a frontier-sparse kernel could skip,
-    sum_k (1 - nnz(N^{k-1}(S)) / nnz) / K (step k gathers T_{k-1}).
+    sum_k (1 - nnz(N^{k-1}(S)) / nnz) / K (step k gathers T_{k-1}).  Measured:
+    gs_heat_apply (and gs_sinkhorn where the workload has pairs) with the
+    option off and on, the level sweeps included, and whether the two runs
+    agree bit for bit.
     """
     import numpy as np
     import scipy.sparse as sp
@@ -614,26 +618,85 @@ def frontier_study(args):
         return {"rows_reached": [round(x, 4) for x in rows[:5]], "nnz_reached": [round(x, 4) for x in nnzs[:5]],
                 "max_skippable_gather_share": round(skip, 4)}
 
+    import torch
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    def measured(g, K, H, pair=None, J=20, t=2.0):
+        """Milliseconds of gs_heat_apply on H (and of gs_sinkhorn on pair, J
+        iterations) with the frontier option off and on, the results compared
+        bit for bit."""
+        Hd = dev(H)
+        B = H.shape[1]
+        plan = gs.Plan(g, K, B)
+        lam = g.edge_bound
+        out = {}
+        Ys = []
+        for fr in (0, 1):
+            plan.set_frontier(fr)
+            Y = torch.empty(H.size, device="cuda")
+            out[f"heat_ms_frontier_{'on' if fr else 'off'}"] = round(
+                timed(lambda: gs.gs_heat_apply(plan, lam, t, Hd, Y)), 3)
+            Ys.append(Y)
+        out["heat_bitwise_equal"] = bool(torch.equal(Ys[0].view(torch.int32), Ys[1].view(torch.int32)))
+        if pair is not None:
+            mu_d, nu_d = dev(pair[0]), dev(pair[1])
+            Ds = []
+            for fr in (0, 1):
+                plan.set_frontier(fr)
+                box = {}
+                out[f"sinkhorn_J{J}_ms_frontier_{'on' if fr else 'off'}"] = round(
+                    timed(lambda: box.update(gs.gs_sinkhorn(plan, lam, t, mu_d, nu_d, J)), reps=3), 3)
+                Ds.append(box["dist"])
+            out["sinkhorn_bitwise_equal"] = bool(np.array_equal(Ds[0], Ds[1]))
+        plan.destroy()
+        return out
+
     res = {"study": "frontier", "workloads": {}}
     X, labels, mu, nu = synth.curve_pair_workload()
     g = gs.gs_graph_from_points(X, 15)
     rp, col, _, _ = g.export()
-    res["workloads"]["100k curve, one pair (mu on clusters 0-3), K = 30"] = reach(rp, col, mu > 0, 30)
+    key = "100k curve, one pair (mu on clusters 0-3), K = 30"
+    res["workloads"][key] = reach(rp, col, mu > 0, 30)
+    res["workloads"][key].update(measured(g, 30, mu[:, None], pair=(mu[:, None], nu[:, None])))
     X, labels, _ = synth.barycenter_workload()
     g = gs.gs_graph_from_points(X, 15)
     rp, col, _, _ = g.export()
     gm, gn = synth.gradient_pairs(labels)
-    res["workloads"]["200k gradients, 32 pairs (union of the mu supports), K = 30"] = reach(rp, col, (gm > 0).any(axis=1), 30)
-    res["workloads"]["200k gradients, pair 0 alone, K = 30"] = reach(rp, col, gm[:, 0] > 0, 30)
+    key = "200k gradients, 32 pairs (union of the mu supports), K = 30"
+    res["workloads"][key] = reach(rp, col, (gm > 0).any(axis=1), 30)
+    res["workloads"][key].update(measured(g, 30, gm, pair=(gm, gn)))
+    key = "200k gradients, pair 0 alone, K = 30"
+    res["workloads"][key] = reach(rp, col, gm[:, 0] > 0, 30)
+    res["workloads"][key].update(measured(g, 30, gm[:, :1], pair=(gm[:, :1], gn[:, :1])))
     X, labels = synth.clusters_on_surface((10, 5), args.per_cluster, 100, 0.1, workload=5)
     g = gs.gs_graph_from_points(X, args.knn)
     rp, col, _, _ = g.export()
     n = rp.shape[0] - 1
     sizes = synth.loguniform_support_sizes(n, 256, 5000, 200000, synth.seed_for(5, 2))
-    S = np.zeros(n, dtype=bool)
+    H = np.zeros((n, 32), dtype=np.float32)
     for i in range(32):
-        S |= synth.histogram_on_random_support(n, int(sizes[i]), 1.0, synth.seed_for(5, 2) * 1000 + i) > 0
-    res["workloads"]["1M kNN, a batch of 32 random supports, K = 50"] = reach(rp, col, S, 50)
+        H[:, i] = synth.histogram_on_random_support(n, int(sizes[i]), 1.0, synth.seed_for(5, 2) * 1000 + i)
+    key = "1M kNN, a batch of 32 random supports, K = 50"
+    res["workloads"][key] = reach(rp, col, (H > 0).any(axis=1), 50)
+    res["workloads"][key].update(measured(g, 50, H))
+    nc = 1_000_000
+    gc = gs.gs_graph_from_csr(nc, *synth.cycle_graph(nc))
+    Hc = np.zeros((nc, 1), dtype=np.float32)
+    Hc[nc // 2, 0] = 1.0
+    res["workloads"]["1M cycle, one node, K = 50 (the most localised case)"] = measured(gc, 50, Hc)
     print(json.dumps(res), flush=True)
 
 

@@ -60,6 +60,7 @@ _SIGS = {
     "gs_plan_set_shape": (C.c_int, [c_plan, C.c_int32, C.c_int32, C.c_int32]),
     "gs_plan_set_kernel": (C.c_int, [c_plan, C.c_int32, C.c_int32, C.c_int32]),
     "gs_plan_set_csr_hint": (C.c_int, [c_plan, C.c_int32]),
+    "gs_plan_set_frontier": (C.c_int, [c_plan, C.c_int32]),
     "gs_plan_describe": (C.c_int, [c_plan, C.c_char_p, C.c_int32]),
     "gs_plan_destroy": (None, [c_plan]),
     "gs_heat_apply": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f32, c_stream]),

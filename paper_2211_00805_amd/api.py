@@ -164,6 +164,10 @@ class Plan:
         """gs_plan_set_csr_hint: CSR read with non-temporal hints (streamed) or with cached loads."""
         check("gs_plan_set_csr_hint", lib.gs_plan_set_csr_hint(self.handle, int(bool(streamed))))
 
+    def set_frontier(self, enable: bool) -> None:
+        """gs_plan_set_frontier: skip rows beyond k hops of the applied supports at step k (bitwise the dense result)."""
+        check("gs_plan_set_frontier", lib.gs_plan_set_frontier(self.handle, int(bool(enable))))
+
     def set_kernel(self, kernel: int, N: int = 0, cg_iters: int = 0) -> None:
         """gs_plan_set_kernel: Chebyshev (default) or backward-Euler (N solves of cg_iters CG steps, 0 = auto)."""
         check("gs_plan_set_kernel", lib.gs_plan_set_kernel(self.handle, int(kernel), int(N), int(cg_iters)))

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgeosink.so")
-SOURCES = ["kernels.hip", "euler.hip", "measure.hip", "accumulate.hip", "validate.hip", "knn.hip", "noalloc.hip", "coeffs.cpp", "graph.cpp", "plan.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "euler.hip", "measure.hip", "accumulate.hip", "validate.hip", "knn.hip", "noalloc.hip", "frontier.hip", "coeffs.cpp", "graph.cpp", "plan.cpp", "abi.cpp"]
 ARCH = "gfx950"
 
 

@@ -208,6 +208,16 @@ gs_status gs_plan_set_csr_hint(gs_plan p, int32_t streamed) {
     });
 }
 
+gs_status gs_plan_set_frontier(gs_plan p, int32_t enable) {
+    return guarded([&] {
+        GS_REQUIRE(p != nullptr, "plan is NULL");
+        GS_REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+        GS_HIP(hipDeviceSynchronize());
+        drop_graphs(*p);
+        set_frontier(*p, enable);
+    });
+}
+
 gs_status gs_plan_set_kernel(gs_plan p, int32_t kernel, int32_t N, int32_t cg_iters) {
     return guarded([&] {
         GS_REQUIRE(p != nullptr, "plan is NULL");
@@ -228,7 +238,7 @@ gs_status gs_plan_describe(gs_plan p, char* buf, int32_t len) {
         const std::string s = "vec=" + std::to_string(p->shape.vec) + " S=" + std::to_string(p->shape.S) +
                               " C=" + std::to_string(p->shape.C) + " xcd=" + std::to_string(p->shape.remap) +
                               (p->shape.csr_nt ? " csr=nt" : " csr=t") +
-                              " ldp=" + std::to_string(p->ldp) +
+                              " ldp=" + std::to_string(p->ldp) + (p->frontier ? " frontier=on" : "") +
                               " origin=" + p->shape_origin + ((p->flags & GS_PLAN_NO_GRAPH) ? " graphs=off" : " graphs=on") +
                               (p->kernel == GS_KERNEL_EULER
                                    ? " kernel=euler N=" + std::to_string(p->euler_N) + " cg=" +

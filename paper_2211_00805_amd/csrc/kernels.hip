@@ -233,9 +233,33 @@ __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off,
     }
 }
 
+// Frontier rows (level above the step index) have all-zero operands and
+// skip their gathers.  A whole block of them in the accumulating forms also
+// skips its own loads: those forms give +0 from any zeros they read.
+// Clenshaw's recurrence can carry -0 through such rows, so there they still
+// load their own operands, and every form keeps the dense kernel's bits,
+// signs of zeros included.
+template <int MODE>
+__device__ __forceinline__ bool row_loads_needed(bool block_dead) {
+    return !block_dead || MODE == kModeClen;
+}
+
+// Step k < K, row at level k: neighbour j (and its row block of RPB rows)
+// moves to level k + 1 unless it is already that close.  Every writer of a
+// launch stores the same value.
+template <int RPB>
+__device__ __forceinline__ void frontier_push(const StepArgs& A, int j) {
+    const int nl = A.k + 1;
+    if ((int)A.level[j] > nl) {
+        A.level[j] = (uint8_t)nl;
+        if ((int)A.blk_level[j / RPB] > nl) A.blk_level[j / RPB] = (uint8_t)nl;
+    }
+}
+
 // Rows with more than A.long_thr nonzeros: one block per row and column tile,
-// 256/C lanes splitting the nonzeros, a block reduction through LDS.
-template <int VEC, int C, int MODE>
+// 256/C lanes splitting the nonzeros, a block reduction through LDS.  FR: the
+// frontier form (A.level set).
+template <int VEC, int C, int MODE, int RPB, bool FR>
 __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int ncoltiles, float* red_lds) {
     constexpr int SL = kBlock / C;   // lanes over the nonzeros
     float (*red)[C][VEC + 1] = reinterpret_cast<float (*)[C][VEC + 1]>(red_lds);
@@ -249,9 +273,13 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     const int colofs = (item - li * ncoltiles) * (VEC * C) + c * VEC;
     const bool colok = colofs < A.ldp;   // lanes past the padded row stay idle
     const size_t off = (size_t)row * A.ldp + (colok ? colofs : 0);
+    const int lv = FR ? (int)A.level[row] : 0;   // block-uniform
+    const bool dead = FR && lv > A.k;
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
-    if (s == 0 && colok) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
-    const int rs = A.rowptr[row], re = colok ? A.rowptr[row + 1] : rs;
+    if (s == 0 && colok && row_loads_needed<MODE>(dead)) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
+    const int rs = A.rowptr[row], re = (colok && !dead) ? A.rowptr[row + 1] : rs;
+    if (FR && lv == A.k && A.k < A.K && item == li * ncoltiles && c == 0)
+        for (int e = rs + s; e < re; e += SL) frontier_push<RPB>(A, A.col[e]);
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
     float sw = 0.f;
@@ -296,7 +324,7 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     }
 }
 
-template <int VEC, int S, int C, int MODE>
+template <int VEC, int S, int C, int MODE, bool FR>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     constexpr int LPR = S * C;       // lanes per row
     constexpr int RPW = 64 / LPR;    // rows per wave
@@ -309,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     // the first blocks take the long rows (dispatched first, they overlap the tiles)
     const int nlb = A.nlong * ncoltiles;
     if ((int)blockIdx.x < nlb) {
-        long_row_block<VEC, C, MODE>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
+        long_row_block<VEC, C, MODE, RPB, FR>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
         return;
     }
     const int bt = (int)blockIdx.x - nlb;
@@ -327,20 +355,24 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const bool valid = row < A.n && colofs < ldp;
     const size_t off = (size_t)(valid ? row : r0) * ldp + (colofs < ldp ? colofs : 0);
 
+    // frontier: a block whose rows all lie beyond step k's reach reads no CSR
+    // (the block and row levels load beside the row pointers)
     const int eb = A.rowptr[r0];
-    const int ee = A.rowptr[r1];
+    int ee = A.rowptr[r1];
+    const bool blk_dead = FR && (int)A.blk_level[rt] > A.k;
+    if (blk_dead) ee = eb;
     int rs = 0, re = 0;
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
     bool longrow = false;
+    bool push = false;   // this row is at level k: it advances the frontier
     if (valid) {
         rs = A.rowptr[row];
         re = A.rowptr[row + 1];
+        const int lv = FR ? (int)A.level[row] : 0;
         longrow = A.long_thr > 0 && re - rs > A.long_thr;
-        if (longrow) {
-            re = rs;   // taken by a long-row block at the head of the grid
-        } else {
-            load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
-        }
+        if (longrow || (FR && (blk_dead || lv > A.k))) re = rs;   // long rows: taken by a long-row block at the head of the grid
+        if (!longrow && row_loads_needed<MODE>(blk_dead)) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
+        push = FR && !blk_dead && !longrow && lv == A.k && A.k < A.K && ct == 0 && c == 0;
     }
 
     Vec<VEC> sx = vzero<VEC>();
@@ -362,8 +394,8 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         const int hi = re < cend ? re : cend;
         if (valid && lo < hi) {
             // first e >= lo with (e - rs) % S == s
-            int e = lo + (((s - (lo - rs)) % S) + S) % S;
-            for (; e < hi; e += kUnroll * S) {
+            const int e0 = lo + (((s - (lo - rs)) % S) + S) % S;
+            for (int e = e0; e < hi; e += kUnroll * S) {
                 Vec<VEC> x[kUnroll];
                 float w[kUnroll];
 #pragma unroll
@@ -382,6 +414,8 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
                     for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], x[u].v[i], sx.v[i]);
                 }
             }
+            if (push)
+                for (int e = e0; e < hi; e += S) frontier_push<RPB>(A, stage[e - cb].x);
         }
         __syncthreads();
     }
@@ -396,18 +430,26 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     step_epilogue<VEC, MODE>(A, row, off, own, p2, ac, ac2, sx, sw);
 }
 
+template <int VEC, int S, int C, bool FR>
+void launch_mode(const StepArgs& a, int grid, hipStream_t st) {
+    if (a.flags & STEP_CLENSHAW)
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeClen, FR>), dim3(grid), dim3(kBlock), 0, st, a);
+    else if (a.flags & STEP_DUAL)
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeDual, FR>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeFwd, FR>), dim3(grid), dim3(kBlock), 0, st, a);
+}
+
 template <int VEC, int S, int C>
 void launch_shape(const StepArgs& a, hipStream_t st) {
     constexpr int RPB = 4 * (64 / (S * C));
     const int nrt = (a.n + RPB - 1) / RPB;
     const int nct = (a.ldp + VEC * C - 1) / (VEC * C);
     const int grid = nrt * nct + a.nlong * nct;
-    if (a.flags & STEP_CLENSHAW)
-        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeClen>), dim3(grid), dim3(kBlock), 0, st, a);
-    else if (a.flags & STEP_DUAL)
-        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeDual>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.level)
+        launch_mode<VEC, S, C, true>(a, grid, st);
     else
-        hipLaunchKernelGGL((cheb_step_kernel<VEC, S, C, kModeFwd>), dim3(grid), dim3(kBlock), 0, st, a);
+        launch_mode<VEC, S, C, false>(a, grid, st);
 }
 
 // ------------------------------------------------------------------ small kernels

@@ -60,7 +60,7 @@ void run_graph(gs_plan_s& P, const std::string& key, hipStream_t st, F&& body) {
     const std::string full = (P.kernel == GS_KERNEL_EULER
                                   ? key + ":E" + std::to_string(P.euler_N) + "." + std::to_string(P.cg_m)
                                   : key) +
-                             (P.count_floors ? ":F" : "");
+                             (P.count_floors ? ":F" : "") + (P.frontier ? ":R" : "");
     auto it = P.graphs.find(full);
     if (it == P.graphs.end()) {
         GS_HIP(hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal));
@@ -351,8 +351,10 @@ double step_bytes(const gs_plan_s& P, const StepSched& sc, bool has_out_a, bool 
 namespace {
 
 void enqueue_cheb_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi,
-                        hipStream_t st) {
-    const StepArgs base = base_args(P);
+                        hipStream_t st, Levels lev = Levels{}) {
+    StepArgs base = base_args(P);
+    base.level = lev.row;
+    base.blk_level = lev.blk;
     const std::vector<StepSched> sched = step_schedule(P.K, mode);
     for (int k = 1; k <= P.K; ++k) {
         StepArgs a = base;
@@ -377,8 +379,10 @@ void enqueue_cheb_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Scal
 // p_K X by Clenshaw's recurrence into ACC (or scaled into epi.out); u_k
 // rotates through U and V like T_k, written over u_{k+2} in place.
 void enqueue_clenshaw_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi,
-                            hipStream_t st) {
-    const StepArgs base = base_args(P);
+                            hipStream_t st, Levels lev = Levels{}) {
+    StepArgs base = base_args(P);
+    base.level = lev.row;
+    base.blk_level = lev.blk;
     const std::vector<StepSched> sched = clenshaw_schedule(P.K, mode);
     for (int j = 1; j <= P.K; ++j) {
         StepArgs a = base;
@@ -441,14 +445,49 @@ void enqueue_euler_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Sca
 
 }  // namespace
 
-void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st) {
+// `lev`: frontier levels of a superset of supp(X), set up by enqueue_levels
+// (row == nullptr: dense steps); the results are the dense ones bit for bit.
+void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st,
+                   Levels lev) {
     if (P.kernel == GS_KERNEL_EULER)
         enqueue_euler_apply(P, X, mode, epi, phi, st);
     else if (P.kernel == GS_KERNEL_CLENSHAW && mode != ApplyMode::Dual)
-        enqueue_clenshaw_apply(P, X, mode, epi, phi, st);   // the dual form needs the accumulators
+        enqueue_clenshaw_apply(P, X, mode, epi, phi, st, lev);   // the dual form needs the accumulators
     else
-        enqueue_cheb_apply(P, X, mode, epi, phi, st);
+        enqueue_cheb_apply(P, X, mode, epi, phi, st, lev);
 }
+
+void set_frontier(gs_plan_s& P, int enable) {
+    P.frontier = enable;
+    if (enable && !P.lev_mu.p) {
+        const size_t nr = P.n ? (size_t)P.n : 1;
+        const size_t nb = nr / 4 + 1;   // row blocks of the smallest shape (4 rows)
+        P.lev_mu.alloc(nr);
+        P.lev_nu.alloc(nr);
+        P.blk_mu.alloc(nb);
+        P.blk_nu.alloc(nb);
+    }
+}
+
+namespace {
+
+// Frontier steps apply to the polynomial kernels (the conjugate-gradient
+// solves of the Euler kernel have no step index to compare a level with).
+bool frontier_on(const gs_plan_s& P) { return P.frontier && P.kernel != GS_KERNEL_EULER; }
+
+// Frontier levels of supp(h) (rows where any of the B columns is nonzero)
+// before step 1, with row blocks of the plan's launch shape; the steps of an
+// application advance them (an application from the same support finds them
+// already advanced, which changes nothing).
+void enqueue_levels(gs_plan_s& P, const float* h, Levels lev, hipStream_t st) {
+    const int rpb = 4 * (64 / (P.shape.S * P.shape.C));
+    launch_support_levels(h, P.n, P.ldp, P.B, P.g->rowptr.p, P.g->col.p, rpb, lev.row, lev.blk, st);
+}
+
+Levels levels_mu(gs_plan_s& P) { return {P.lev_mu.p, P.blk_mu.p}; }
+Levels levels_nu(gs_plan_s& P) { return {P.lev_nu.p, P.blk_nu.p}; }
+
+}  // namespace
 
 // Average duration (ms) of one step launch over `reps` whole applications of
 // p_K (the accumulator form, or Clenshaw's when the plan selects it), and
@@ -564,8 +603,11 @@ void heat_apply(gs_plan_s& P, double lam, double t, const float* X, float* Y, fl
     if (dual && !P.ACC2.p) P.ACC2.alloc(P.sz());
     set_coefs(P, lam, t, st);
     launch_copy_ld(X, P.B, P.X.p, P.ldp, P.n, P.B, st);
+    const bool fr = frontier_on(P);
     run_graph(P, dual ? "heat:dual" : "heat", st, [&](hipStream_t s) {
-        enqueue_apply(P, P.X.p, dual ? ApplyMode::Dual : ApplyMode::Store, ScaleEpi{}, 0.f, s);
+        if (fr) enqueue_levels(P, P.X.p, levels_mu(P), s);
+        enqueue_apply(P, P.X.p, dual ? ApplyMode::Dual : ApplyMode::Store, ScaleEpi{}, 0.f, s,
+                      fr ? levels_mu(P) : Levels{});
     });
     launch_copy_ld(P.ACC.p, P.ldp, Y, P.B, P.n, P.B, st);
     if (dual) launch_copy_ld(P.ACC2.p, P.ldp, Ydt, P.B, P.n, P.B, st);
@@ -589,11 +631,14 @@ void load_inputs(gs_plan_s& P, const float* a, const float* mu, const float* nu,
 }
 
 // One Sinkhorn iteration: v = mu / floor(p_K(a w)), w = nu / floor(p_K(a v)).
-void enqueue_iteration(gs_plan_s& P, bool has_a, float phi, float* rec_d, float* rec_e, hipStream_t s) {
+// lev_w, lev_v: hop levels of supersets of supp(a w) and supp(a v) for
+// frontier steps, or nullptr.
+void enqueue_iteration(gs_plan_s& P, bool has_a, float phi, float* rec_d, float* rec_e, hipStream_t s,
+                       Levels lev_w = Levels{}, Levels lev_v = Levels{}) {
     ScaleEpi e1{P.mu.p, P.v.p, has_a ? P.xv.p : nullptr, has_a ? P.a.p : nullptr, rec_d};
-    enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Scale, e1, phi, s);
+    enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Scale, e1, phi, s, lev_w);
     ScaleEpi e2{P.nu.p, P.w.p, has_a ? P.xw.p : nullptr, has_a ? P.a.p : nullptr, rec_e};
-    enqueue_apply(P, has_a ? P.xv.p : P.v.p, ApplyMode::Scale, e2, phi, s);
+    enqueue_apply(P, has_a ? P.xv.p : P.v.p, ApplyMode::Scale, e2, phi, s, lev_v);
 }
 
 void reduce_to_host(gs_plan_s& P, const ReduceArgs& r, double scale, double* host, hipStream_t st) {
@@ -664,6 +709,15 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
     launch_fill(P.w.p, 1.f, P.sz(), st);
     if (has_a) launch_mul_a(P.w.p, P.a.p, P.n, P.ldp, P.xw.p, st);
     GS_HIP(hipMemsetAsync(P.nfloor.p, 0, sizeof(unsigned long long), st));
+    // frontier steps: a v lies on supp(mu), and a w on supp(nu) once the first
+    // iteration has replaced w = 1 (the quotients vanish with their numerators)
+    const bool fr = frontier_on(P);
+    if (fr) {
+        enqueue_levels(P, P.mu.p, levels_mu(P), st);
+        enqueue_levels(P, P.nu.p, levels_nu(P), st);
+    }
+    const Levels lev_v = fr ? levels_mu(P) : Levels{};
+    auto lev_w = [&](int j) { return fr && j > 0 ? levels_nu(P) : Levels{}; };
     const std::string key = std::string("fwd:") + (has_a ? "a" : "1") + phi_tag(phi);
     if (ckpt && C == GS_RECORD_ALL) {
         // every iteration's floored denominators d_j, e_j into slots 2j, 2j+1
@@ -676,21 +730,24 @@ void sinkhorn(gs_plan_s& P, double lam, double t, const float* a, const float* m
                       [&](hipStream_t s) {
                           for (int j = j0; j < j0 + ns; ++j)
                               enqueue_iteration(P, has_a, phi, ckpt + 2 * (size_t)j * sz,
-                                                ckpt + (2 * (size_t)j + 1) * sz, s);
+                                                ckpt + (2 * (size_t)j + 1) * sz, s, lev_w(j), lev_v);
                       });
         }
     } else {
         for (int j = 0; j < J; ++j) {
             if (ckpt && j % C == 0)
                 launch_copy_ld(P.w.p, P.ldp, ckpt + (size_t)(j / C) * P.n * P.B, P.B, P.n, P.B, st);
-            run_graph(P, key, st, [&](hipStream_t s) { enqueue_iteration(P, has_a, phi, nullptr, nullptr, s); });
+            run_graph(P, fr && j == 0 ? key + ":first" : key, st, [&](hipStream_t s) {
+                enqueue_iteration(P, has_a, phi, nullptr, nullptr, s, lev_w(j), lev_v);
+            });
         }
     }
     const float* ap = has_a ? P.a.p : nullptr;
     if (dist) reduce_to_host(P, red_args(P, RED_DIST, P.mu.p, P.v.p, P.nu.p, P.w.p, ap), 4.0 * t, dist, st);
     if (marg) {
-        run_graph(P, std::string("marg:") + (has_a ? "a" : "1") + phi_tag(phi), st, [&](hipStream_t s) {
-            enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Store, ScaleEpi{}, phi, s);
+        const std::string mkey = std::string("marg:") + (has_a ? "a" : "1") + phi_tag(phi);
+        run_graph(P, mkey, st, [&](hipStream_t s) {
+            enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Store, ScaleEpi{}, phi, s, lev_w(J));
         });
         reduce_to_host(P, red_args(P, RED_MARG, P.v.p, P.ACC.p, P.mu.p, nullptr, ap), 1.0, marg, st);
     }
@@ -868,7 +925,7 @@ void barycenter(gs_plan_s& P, double lam, double t, const float* a, const float*
     if (v) launch_copy_ld(P.v.p, P.ldp, v, P.B, P.n, P.B, st);
     if (w) launch_copy_ld(P.w.p, P.ldp, w, P.B, P.n, P.B, st);
     if (marg) {
-        run_graph(P, std::string("marg:") + (has_a ? "a" : "1") + phi_tag(phi), st, [&](hipStream_t s) {
+        run_graph(P, std::string("bmarg:") + (has_a ? "a" : "1") + phi_tag(phi), st, [&](hipStream_t s) {
             enqueue_apply(P, has_a ? P.xw.p : P.w.p, ApplyMode::Store, ScaleEpi{}, phi, s);
         });
         reduce_to_host(P, red_args(P, RED_MARG, P.v.p, P.ACC.p, P.mu.p, nullptr, ap), 1.0, marg, st);

@@ -18,6 +18,13 @@ struct StepSched {
     int cmask;
 };
 
+// Frontier levels of one support (rows, row blocks of the plan's shape);
+// row == nullptr: dense steps.
+struct Levels {
+    uint8_t* row = nullptr;
+    uint8_t* blk = nullptr;
+};
+
 struct ScaleEpi {
     const float* num = nullptr;
     float* out = nullptr;
@@ -63,6 +70,11 @@ struct gs_plan_s {
     gs::DevBuf<float> er, ep, eq, ecoef;   // CG residual, direction, product; operator scale
     gs::DevBuf<double> ers;                // per-column rr (two slots), p.qn, then column-pass partials
 
+    // frontier-sparse steps (opt-in): per-row hop levels of the supports the
+    // applications start from (mu's also serves gs_heat_apply's X)
+    int frontier = 0;
+    gs::DevBuf<uint8_t> lev_mu, lev_nu, blk_mu, blk_nu;
+
     std::map<std::string, hipGraphExec_t> graphs;
     std::map<std::string, hipGraph_t> graph_defs;
 
@@ -74,7 +86,9 @@ namespace gs {
 
 gs_plan_s* plan_create(gs_graph g, int K, int B, int flags, const char* tune_cache);
 void set_coefs(gs_plan_s& P, double lambda_hat, double t, hipStream_t st);
-void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st);
+void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi& epi, float phi, hipStream_t st,
+                   Levels lev = Levels{});
+void set_frontier(gs_plan_s& P, int enable);
 void set_kernel(gs_plan_s& P, int kernel, int N, int cg_iters);
 int euler_cg_iterations(double t, int N);
 void heat_apply(gs_plan_s& P, double lam, double t, const float* X, float* Y, float* Ydt, hipStream_t st);

@@ -99,6 +99,8 @@ def test_validation_rejects_before_any_device_call():
     assert b"NULL" in lib.gs_last_error()
     assert lib.gs_plan_set_csr_hint(None, 1) == -1
     assert b"plan is NULL" in lib.gs_last_error()
+    assert lib.gs_plan_set_frontier(None, 1) == -1
+    assert b"plan is NULL" in lib.gs_last_error()
     assert lib.gs_heat_apply_noalloc(None, 2.0, 1.0, 10, None, None, 4, None) == -1
     assert b"graph is NULL" in lib.gs_last_error()
 

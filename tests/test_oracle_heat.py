@@ -144,3 +144,47 @@ def test_lambda_hat_below_the_spectrum_voids_the_truncation_bound():
         assert (err <= tail * nx + 1e-12) == bounded, (ratio, err, tail * nx)
         assert (np.linalg.norm(y) <= (1 + tail) * nx) == contraction, ratio
         assert abs(y.sum() - p0 * x.sum()) <= 1e-9 * max(np.abs(y).sum(), 1.0), ratio
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 12])
+def test_application_is_local_to_K_hops(K):
+    """p_K(L, t) x vanishes exactly beyond K hops of supp(x) and not at K hops.
+
+    y = (2/lambda_hat) L - I couples a node only to itself and its neighbours
+    (Sec. "Chebyshev Polynomials"), so T_k(y) x lives on the k-hop
+    neighbourhood of supp(x): the fact the frontier-sparse steps rely on.  On a
+    path from one end node, the value K hops out is the single walk's weight
+    b_K 2^(K-1) (2/lambda_hat)^K prod(-w) (nonzero); every row farther out is
+    exactly 0.0.  On a graph with hub rows (and a small diameter), every row
+    beyond min(K, 4) hops of a three-node support is exactly 0.0 at that
+    degree, and some row at that distance is not.
+    """
+    n, t = 40, 1.5
+    i = np.arange(n - 1)
+    w = np.linspace(0.5, 1.5, n - 1)
+    A = sp.csr_matrix((np.concatenate([w, w]), (np.concatenate([i, i + 1]), np.concatenate([i + 1, i]))),
+                      shape=(n, n))
+    L = graph.laplacian(A)
+    lam = 1.01 * spectrum.lambda_max(L)
+    x = np.zeros(n)
+    x[0] = 1.0
+    y = heat.heat_apply(L, lam, t, K, x)
+    assert np.all(y[K + 1:] == 0.0)
+    b = heat.cheb_coeffs(t, K)
+    walk = b[K] * 2.0 ** (K - 1) * (2.0 / lam) ** K * np.prod(-w[:K])
+    assert y[K] == pytest.approx(walk, rel=1e-12) and y[K] != 0.0
+
+    m = 3000
+    arrs = synth.random_local_graph(m, 4, 40, np.random.default_rng(K), hubs=2, hub_degree=300)
+    G = csr(arrs, m)
+    Lg = graph.laplacian(G)
+    X = np.zeros((m, 2))
+    X[[5, 1700], 0] = [1.0, 2.0]
+    X[2900, 1] = 0.5
+    hops = sp.csgraph.shortest_path(G, unweighted=True, indices=[5, 1700, 2900]).min(axis=0)
+    Kg = min(K, 4)
+    Y = heat.heat_apply(Lg, Lg.diagonal().max() * 2.0, t, Kg, X)
+    assert np.count_nonzero(hops > Kg) > 100
+    assert np.all(Y[hops > Kg] == 0.0)
+    assert np.any(Y[hops == Kg] != 0.0)
+
