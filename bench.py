@@ -593,9 +593,9 @@ def frontier_study(args):
     nonzeros (the gathers) inside N^k(S) for k = 0..4, and the largest share
     of an application's gathers a frontier-sparse kernel could skip,
     sum_k (1 - nnz(N^{k-1}(S)) / nnz) / K (step k gathers T_{k-1}).  Measured:
-    gs_heat_apply (and gs_sinkhorn where the workload has pairs) with the
-    option off and on, the level sweeps included, and whether the two runs
-    agree bit for bit.
+    gs_heat_apply (and gs_sinkhorn, J = 6, where the workload has pairs) on a
+    plan with the frontier option and one without, calls interleaved, the
+    level computation included, and whether the two agree bit for bit.
     """
     import numpy as np
     import scipy.sparse as sp
@@ -623,45 +623,51 @@ def frontier_study(args):
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
-    def timed(fn, reps=5):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        return float(np.median(ts)) * 1e3
-
-    def measured(g, K, H, pair=None, J=20, t=2.0):
+    def measured(g, K, H, pair=None, J=6, t=2.0, rounds=15):
         """Milliseconds of gs_heat_apply on H (and of gs_sinkhorn on pair, J
-        iterations) with the frontier option off and on, the results compared
-        bit for bit."""
+        iterations) on a plan with the frontier option off and one with it
+        on, the calls interleaved round by round (medians), the results
+        compared bit for bit."""
         Hd = dev(H)
         B = H.shape[1]
-        plan = gs.Plan(g, K, B)
         lam = g.edge_bound
+        plans = (gs.Plan(g, K, B), gs.Plan(g, K, B))
+        plans[1].set_frontier(1)
+        Ys = [torch.empty(H.size, device="cuda") for _ in plans]
+        pd = None if pair is None else (dev(pair[0]), dev(pair[1]))
+        dist = [None, None]
+
+        def call(i, what):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if what == "heat":
+                gs.gs_heat_apply(plans[i], lam, t, Hd, Ys[i])
+            else:
+                dist[i] = gs.gs_sinkhorn(plans[i], lam, t, pd[0], pd[1], J)["dist"]
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3
+
+        whats = ["heat"] + (["sinkhorn"] if pair is not None else [])
+        for w in whats:
+            for i in (0, 1):
+                call(i, w)
+        ts = {(w, i): [] for w in whats for i in (0, 1)}
+        for _ in range(rounds):
+            for w in whats:
+                for i in (0, 1):
+                    ts[(w, i)].append(call(i, w))
         out = {}
-        Ys = []
-        for fr in (0, 1):
-            plan.set_frontier(fr)
-            Y = torch.empty(H.size, device="cuda")
-            out[f"heat_ms_frontier_{'on' if fr else 'off'}"] = round(
-                timed(lambda: gs.gs_heat_apply(plan, lam, t, Hd, Y)), 3)
-            Ys.append(Y)
+        for w in whats:
+            name = "heat" if w == "heat" else f"sinkhorn_J{J}"
+            off, on = float(np.median(ts[(w, 0)])), float(np.median(ts[(w, 1)]))
+            out[f"{name}_ms_frontier_off"] = round(off, 3)
+            out[f"{name}_ms_frontier_on"] = round(on, 3)
+            out[f"{name}_on_over_off"] = round(on / off, 3)
         out["heat_bitwise_equal"] = bool(torch.equal(Ys[0].view(torch.int32), Ys[1].view(torch.int32)))
         if pair is not None:
-            mu_d, nu_d = dev(pair[0]), dev(pair[1])
-            Ds = []
-            for fr in (0, 1):
-                plan.set_frontier(fr)
-                box = {}
-                out[f"sinkhorn_J{J}_ms_frontier_{'on' if fr else 'off'}"] = round(
-                    timed(lambda: box.update(gs.gs_sinkhorn(plan, lam, t, mu_d, nu_d, J)), reps=3), 3)
-                Ds.append(box["dist"])
-            out["sinkhorn_bitwise_equal"] = bool(np.array_equal(Ds[0], Ds[1]))
-        plan.destroy()
+            out["sinkhorn_bitwise_equal"] = bool(np.array_equal(dist[0], dist[1]))
+        for p in plans:
+            p.destroy()
         return out
 
     res = {"study": "frontier", "workloads": {}}
@@ -677,7 +683,7 @@ def frontier_study(args):
     gm, gn = synth.gradient_pairs(labels)
     key = "200k gradients, 32 pairs (union of the mu supports), K = 30"
     res["workloads"][key] = reach(rp, col, (gm > 0).any(axis=1), 30)
-    res["workloads"][key].update(measured(g, 30, gm, pair=(gm, gn)))
+    res["workloads"][key].update(measured(g, 30, gm, pair=(gm, gn), rounds=6))
     key = "200k gradients, pair 0 alone, K = 30"
     res["workloads"][key] = reach(rp, col, gm[:, 0] > 0, 30)
     res["workloads"][key].update(measured(g, 30, gm[:, :1], pair=(gm[:, :1], gn[:, :1])))
@@ -691,12 +697,14 @@ def frontier_study(args):
         H[:, i] = synth.histogram_on_random_support(n, int(sizes[i]), 1.0, synth.seed_for(5, 2) * 1000 + i)
     key = "1M kNN, a batch of 32 random supports, K = 50"
     res["workloads"][key] = reach(rp, col, (H > 0).any(axis=1), 50)
-    res["workloads"][key].update(measured(g, 50, H))
+    res["workloads"][key].update(measured(g, 50, H, rounds=5))
     nc = 1_000_000
     gc = gs.gs_graph_from_csr(nc, *synth.cycle_graph(nc))
     Hc = np.zeros((nc, 1), dtype=np.float32)
     Hc[nc // 2, 0] = 1.0
-    res["workloads"]["1M cycle, one node, K = 50 (the most localised case)"] = measured(gc, 50, Hc)
+    Hc2 = np.zeros((nc, 1), dtype=np.float32)
+    Hc2[nc // 2 + 20, 0] = 1.0
+    res["workloads"]["1M cycle, one node each (20 hops apart), K = 50"] = measured(gc, 50, Hc, pair=(Hc, Hc2))
     print(json.dumps(res), flush=True)
 
 

@@ -176,20 +176,21 @@ gs_status gs_plan_set_csr_hint(gs_plan p, int32_t streamed);
 /* Frontier-sparse steps (enable = 1; 0, the default, computes every row).
  * T_k(y) x vanishes beyond k hops of supp(x), since y = (2/lambda_hat) L - I
  * couples a node only to its graph neighbours (Sec. "Chebyshev Polynomials").
- * With the option on, each call first marks the supports its applications
- * start from (gs_heat_apply: the rows where any column of X is nonzero;
- * gs_sinkhorn: supp(mu) for the applications to a v, supp(nu) for those to
- * a w after the first iteration, which applies to w = 1 densely) and their
- * neighbours, one pass over the CSR per support; step k < K then advances
- * the frontier by a hop from the CSR it stages anyway.  Step k skips the
- * gathers of rows more than k hops away, and a block of such rows skips its
- * CSR and its own loads.  Results are bitwise those of the dense steps; the
- * option pays where the supports are localised (a single pair on a few
- * clusters) and costs a few percent where they cover the graph.
- * gs_barycenter and the reverse sweep of gs_sinkhorn_backward stay dense; the
- * backward-Euler kernel ignores the option.  Allocates about 2.5 n bytes on
- * first use; cached hipGraphs of the plan are dropped; synchronises the
- * device.  GS_ERR_INVALID unless enable is 0 or 1. */
+ * With the option on, each call first finds the breadth-first hop distances
+ * (up to K) from the supports its applications start from, on the device, a
+ * sweep per hop that returns at once after the frontier empties:
+ * gs_heat_apply from the rows where any column of X is nonzero; gs_sinkhorn
+ * from supp(mu) for the applications to a v and from supp(nu) for those to
+ * a w after the first iteration (which applies to w = 1 densely).  Step k
+ * then skips the gathers of rows more than k hops away, and a block of such
+ * rows skips its CSR.  Results are bitwise those of the dense steps.  The
+ * option pays where supports stay localised for many hops (a few nodes on
+ * a large sparse graph) and costs the distance sweeps and about a
+ * microsecond per step where they cover the graph within a few hops (kNN
+ * graphs).  gs_barycenter and the reverse sweep of gs_sinkhorn_backward stay
+ * dense; the backward-Euler kernel ignores the option.  Allocates about
+ * 10 n bytes on first use; cached hipGraphs of the plan are dropped;
+ * synchronises the device.  GS_ERR_INVALID unless enable is 0 or 1. */
 gs_status gs_plan_set_frontier(gs_plan p, int32_t enable);
 
 /* Kernel a plan applies in gs_heat_apply, gs_sinkhorn and gs_barycenter. */

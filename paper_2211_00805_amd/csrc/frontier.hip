@@ -1,15 +1,15 @@
-// Frontier levels of a support, set up before the first Chebyshev step.
+// Hop levels of a support for the frontier-sparse Chebyshev steps.
 //
 // T_k = T_k(y) x is zero outside the k-hop neighbourhood of supp(x) (y couples
 // a node only to itself and its graph neighbours), so step k can skip the rows
-// more than k hops from the support.  Before step 1 the rows of the support
-// hold level 0, their neighbours level 1 and every other row 255; step k < K
-// then pushes level k + 1 to the neighbours of its level-k rows (in the step
-// kernel, from the CSR it has staged), so at step k every row within k hops
-// holds its exact distance and every other row a level above k.  Block levels
-// (the minimum over a step block's rows) let whole blocks outside the
-// frontier skip their CSR.  All writers of one launch store the same value,
-// so the byte stores need no atomics.
+// more than k hops from the support.  The levels are the breadth-first hop
+// distances from the support up to `depth` (kFarLevel beyond), found level by
+// level: sweep s lowers the neighbours of the rows at level s - 1 that are
+// still farther out to s.  Every writer of a sweep stores the same value s,
+// and a row read as kFarLevel or s by another lane is handled alike, so the
+// stores need no atomics.  A sweep after one that found no new row returns at
+// once.  Block levels (the minimum over a step block's rows) let whole blocks
+// outside the frontier skip their CSR.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -19,7 +19,7 @@ namespace gs {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr uint8_t kFar = 255;
+constexpr int kLanesPerRow = 8;   // lanes sharing a row's nonzeros in a sweep
 
 int blocks_for(int64_t count) {
     int64_t g = (count + kBlk - 1) / kBlk;
@@ -27,55 +27,75 @@ int blocks_for(int64_t count) {
     return (int)(g < 1 ? 1 : g);
 }
 
+// Level 0 where any of the B columns of h is nonzero, kFarLevel elsewhere;
+// flags[s] (s = 0..depth) records whether sweep s found a new row (flags[0]:
+// the support itself, taken as nonempty).
 __global__ __launch_bounds__(kBlk) void support_init_kernel(const float* h, int64_t n, int ldp, int B,
-                                                            uint8_t* level) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+                                                            uint32_t* level, int32_t* flags, int depth) {
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t0 <= depth) flags[t0] = t0 == 0 ? 1 : 0;
+    for (int64_t i = t0; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         bool in = false;
         for (int c = 0; c < B; ++c) in = in || h[i * ldp + c] != 0.f;
-        level[i] = in ? 0 : kFar;
+        level[i] = in ? 0u : kFarLevel;
     }
 }
 
-// Rows off the support with a neighbour on it move to level 1 (a row per
-// thread, its nonzeros four at a time; it stops at the first such neighbour).
-// Only 0 is read as "on the support" and only 1 is written, so rows lowered
-// meanwhile by other threads are read correctly either way.
-__global__ __launch_bounds__(kBlk) void support_neighbours_kernel(const int32_t* rowptr, const int32_t* col,
-                                                                  int64_t n, uint8_t* level) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (level[i] == 0) continue;
+// Sweep s: kLanesPerRow lanes per row; the lanes of a row at level s - 1 walk
+// its nonzeros (each every kLanesPerRow-th, four loads in flight) and lower
+// neighbours still farther out to s.
+__global__ __launch_bounds__(kBlk) void level_sweep_kernel(const int32_t* rowptr, const int32_t* col, int64_t n,
+                                                           uint32_t* level, int32_t* flags, int s) {
+    if (flags[s - 1] == 0) return;   // the frontier is empty: every level is final
+    const int sub = threadIdx.x % kLanesPerRow;
+    const int64_t rows_per_grid = (int64_t)gridDim.x * (kBlk / kLanesPerRow);
+    const uint32_t prev = (uint32_t)(s - 1), cur = (uint32_t)s;
+    bool found = false;
+    for (int64_t i = blockIdx.x * (int64_t)(kBlk / kLanesPerRow) + threadIdx.x / kLanesPerRow; i < n;
+         i += rows_per_grid) {
+        if (level[i] != prev) continue;
         const int e1 = rowptr[i + 1];
-        bool hit = false;
-        for (int e = rowptr[i]; e < e1 && !hit; e += 4) {
+        for (int e = rowptr[i] + sub; e < e1; e += 4 * kLanesPerRow) {
             int j[4];
+            uint32_t l[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) j[u] = e + u < e1 ? col[e + u] : (int)i;
+            for (int u = 0; u < 4; ++u) j[u] = e + u * kLanesPerRow < e1 ? col[e + u * kLanesPerRow] : -1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) hit = hit || level[j[u]] == 0;
+            for (int u = 0; u < 4; ++u) l[u] = j[u] >= 0 ? level[j[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (l[u] > cur) {
+                    level[j[u]] = cur;
+                    found = true;
+                }
         }
-        if (hit) level[i] = 1;
     }
+    if (found) flags[s] = 1;
 }
 
-__global__ __launch_bounds__(kBlk) void block_level_kernel(const uint8_t* level, int64_t n, int rpb,
-                                                           uint8_t* blk_level) {
+__global__ __launch_bounds__(kBlk) void block_level_kernel(const uint32_t* level, int64_t n, int rpb,
+                                                           uint32_t* blk_level) {
     const int64_t nb = (n + rpb - 1) / rpb;
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r1 = (b + 1) * rpb < n ? (b + 1) * rpb : n;
-        int m = kFar;
+        uint32_t m = kFarLevel;
         for (int64_t r = b * rpb; r < r1; ++r) m = level[r] < m ? level[r] : m;
-        blk_level[b] = (uint8_t)m;
+        blk_level[b] = m;
     }
 }
 
 }  // namespace
 
 void launch_support_levels(const float* h, int64_t n, int ldp, int B, const int32_t* rowptr, const int32_t* col,
-                           int rpb, uint8_t* level, uint8_t* blk_level, hipStream_t st) {
-    if (rpb < 1) fail(GS_ERR_INVALID, "rows per block must be positive");
+                           int depth, int rpb, uint32_t* level, uint32_t* blk_level, int32_t* flags, hipStream_t st) {
+    if (rpb < 1 || depth < 1 || depth > GS_MAX_K) fail(GS_ERR_INVALID, "level depth or rows per block out of range");
     if (n == 0) return;
-    hipLaunchKernelGGL(support_init_kernel, dim3(blocks_for(n)), dim3(kBlk), 0, st, h, n, ldp, B, level);
-    hipLaunchKernelGGL(support_neighbours_kernel, dim3(blocks_for(n)), dim3(kBlk), 0, st, rowptr, col, n, level);
+    // the flags are cleared by the first depth + 1 threads of the grid
+    hipLaunchKernelGGL(support_init_kernel, dim3(blocks_for(n > depth + 1 ? n : depth + 1)), dim3(kBlk), 0, st, h,
+                       n, ldp, B, level, flags, depth);
+    for (int s = 1; s <= depth; ++s)
+        hipLaunchKernelGGL(level_sweep_kernel, dim3(blocks_for(n * kLanesPerRow)), dim3(kBlk), 0, st, rowptr, col, n,
+                           level, flags, s);
     hipLaunchKernelGGL(block_level_kernel, dim3(blocks_for((n + rpb - 1) / rpb)), dim3(kBlk), 0, st, level, n, rpb,
                        blk_level);
 }

@@ -110,15 +110,13 @@ struct StepArgs {
     unsigned long long* nfloor;
     const float* xin;     // Clenshaw: the applied signal X (read on every product)
     // frontier (nullptr: every row computed): level[i] is the hop distance of
-    // row i from the applied vector's support where it is at most k, and
-    // above k elsewhere; blk_level[b] the lowest level of row block b (the
-    // shape's rows per block).  Rows above k have all-zero operands: they
-    // skip their gathers, and a block of them its CSR (and, in the
-    // accumulating forms, its own loads); the epilogue runs on zeros.  Step
-    // k < K advances the frontier: rows at level k lower their neighbours'
-    // levels (and blocks') above k + 1 to k + 1.
-    uint8_t* level;
-    uint8_t* blk_level;
+    // row i from the applied vector's support (above K where farther), and
+    // blk_level[b] the lowest level of row block b (the shape's rows per
+    // block).  At step k the rows above k have all-zero operands: they skip
+    // their gathers, and a block of them its CSR; the epilogue runs on the
+    // dense kernel's operands.
+    const uint32_t* level;
+    const uint32_t* blk_level;
 };
 
 struct LaunchShape {
@@ -207,11 +205,13 @@ void launch_cg_dir(const float* r, float* p, const double* rr_old, const double*
 void launch_scale_epilogue(const float* acc, const float* num, float* out, float* out_a, const float* a, float* rec,
                            float phi, unsigned long long* nfloor, int64_t n, int ldp, hipStream_t st);
 
-// frontier levels of a support before step 1 (frontier.hip): level 0 where
-// any of the B columns of h (n x ldp) is nonzero, 1 on their neighbours, 255
-// elsewhere; blk_level[b] = min level over rows [b rpb, (b + 1) rpb)
+// hop levels of a support (frontier.hip): level[i] = breadth-first distance
+// of row i from the rows where any of the B columns of h (n x ldp) is nonzero,
+// exact up to `depth`, kFarLevel beyond; blk_level[b] = min level over rows
+// [b rpb, (b + 1) rpb); flags: depth + 1 ints of scratch
+constexpr uint32_t kFarLevel = 1u << 30;
 void launch_support_levels(const float* h, int64_t n, int ldp, int B, const int32_t* rowptr, const int32_t* col,
-                           int rpb, uint8_t* level, uint8_t* blk_level, hipStream_t st);
+                           int depth, int rpb, uint32_t* level, uint32_t* blk_level, int32_t* flags, hipStream_t st);
 
 // gather-throughput helper (measure.hip): out holds gather_out_floats(m) floats
 int64_t gather_out_floats(int64_t m);

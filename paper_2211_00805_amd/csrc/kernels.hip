@@ -233,33 +233,17 @@ __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off,
     }
 }
 
-// Frontier rows (level above the step index) have all-zero operands and
-// skip their gathers.  A whole block of them in the accumulating forms also
-// skips its own loads: those forms give +0 from any zeros they read.
-// Clenshaw's recurrence can carry -0 through such rows, so there they still
-// load their own operands, and every form keeps the dense kernel's bits,
-// signs of zeros included.
-template <int MODE>
-__device__ __forceinline__ bool row_loads_needed(bool block_dead) {
-    return !block_dead || MODE == kModeClen;
-}
-
-// Step k < K, row at level k: neighbour j (and its row block of RPB rows)
-// moves to level k + 1 unless it is already that close.  Every writer of a
-// launch stores the same value.
-template <int RPB>
-__device__ __forceinline__ void frontier_push(const StepArgs& A, int j) {
-    const int nl = A.k + 1;
-    if ((int)A.level[j] > nl) {
-        A.level[j] = (uint8_t)nl;
-        if ((int)A.blk_level[j / RPB] > nl) A.blk_level[j / RPB] = (uint8_t)nl;
-    }
-}
+// Frontier rows (level above the step index) have all-zero operands: they
+// skip their gathers, whole blocks of them their CSR, and they still load
+// their own operands (issued before any level is known, which keeps the
+// level loads off the blocks' critical path).  The epilogue then computes
+// from the same operands as the dense kernel with zero neighbour sums, which
+// gives the dense kernel's bits, signs of zeros included.
 
 // Rows with more than A.long_thr nonzeros: one block per row and column tile,
 // 256/C lanes splitting the nonzeros, a block reduction through LDS.  FR: the
 // frontier form (A.level set).
-template <int VEC, int C, int MODE, int RPB, bool FR>
+template <int VEC, int C, int MODE, bool FR>
 __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int ncoltiles, float* red_lds) {
     constexpr int SL = kBlock / C;   // lanes over the nonzeros
     float (*red)[C][VEC + 1] = reinterpret_cast<float (*)[C][VEC + 1]>(red_lds);
@@ -273,13 +257,10 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     const int colofs = (item - li * ncoltiles) * (VEC * C) + c * VEC;
     const bool colok = colofs < A.ldp;   // lanes past the padded row stay idle
     const size_t off = (size_t)row * A.ldp + (colok ? colofs : 0);
-    const int lv = FR ? (int)A.level[row] : 0;   // block-uniform
-    const bool dead = FR && lv > A.k;
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
-    if (s == 0 && colok && row_loads_needed<MODE>(dead)) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
+    if (s == 0 && colok) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
+    const bool dead = FR && A.level[row] > (uint32_t)A.k;   // block-uniform
     const int rs = A.rowptr[row], re = (colok && !dead) ? A.rowptr[row + 1] : rs;
-    if (FR && lv == A.k && A.k < A.K && item == li * ncoltiles && c == 0)
-        for (int e = rs + s; e < re; e += SL) frontier_push<RPB>(A, A.col[e]);
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
     float sw = 0.f;
@@ -337,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     // the first blocks take the long rows (dispatched first, they overlap the tiles)
     const int nlb = A.nlong * ncoltiles;
     if ((int)blockIdx.x < nlb) {
-        long_row_block<VEC, C, MODE, RPB, FR>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
+        long_row_block<VEC, C, MODE, FR>(A, blockIdx.x, ncoltiles, reinterpret_cast<float*>(stage));
         return;
     }
     const int bt = (int)blockIdx.x - nlb;
@@ -355,25 +336,27 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const bool valid = row < A.n && colofs < ldp;
     const size_t off = (size_t)(valid ? row : r0) * ldp + (colofs < ldp ? colofs : 0);
 
-    // frontier: a block whose rows all lie beyond step k's reach reads no CSR
-    // (the block and row levels load beside the row pointers)
     const int eb = A.rowptr[r0];
     int ee = A.rowptr[r1];
-    const bool blk_dead = FR && (int)A.blk_level[rt] > A.k;
-    if (blk_dead) ee = eb;
+    // frontier: the block's and the row's levels load beside the row
+    // pointers and are consulted only once every load is issued
+    const uint32_t blv = FR ? A.blk_level[rt] : 0u;
     int rs = 0, re = 0;
+    uint32_t lv = 0u;   // first used after the CSR loads are issued
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
     bool longrow = false;
-    bool push = false;   // this row is at level k: it advances the frontier
     if (valid) {
+        if (FR) lv = A.level[row];
         rs = A.rowptr[row];
         re = A.rowptr[row + 1];
-        const int lv = FR ? (int)A.level[row] : 0;
         longrow = A.long_thr > 0 && re - rs > A.long_thr;
-        if (longrow || (FR && (blk_dead || lv > A.k))) re = rs;   // long rows: taken by a long-row block at the head of the grid
-        if (!longrow && row_loads_needed<MODE>(blk_dead)) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
-        push = FR && !blk_dead && !longrow && lv == A.k && A.k < A.K && ct == 0 && c == 0;
+        if (longrow) {
+            re = rs;   // taken by a long-row block at the head of the grid
+        } else {
+            load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
+        }
     }
+    if (FR && blv > (uint32_t)A.k) ee = eb;   // a block beyond step k's reach reads no CSR
 
     Vec<VEC> sx = vzero<VEC>();
     float sw = 0.f;
@@ -392,7 +375,12 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
         __syncthreads();
         const int lo = rs > cb ? rs : cb;
         const int hi = re < cend ? re : cend;
-        if (valid && lo < hi) {
+        // the level is read here, past the barrier: an empty asm keeps the
+        // compiler from hoisting the comparisons (and the wait for the level
+        // load) above the CSR loads
+        uint32_t lvk = lv;
+        if constexpr (FR) asm volatile("" : "+v"(lvk));
+        if (valid && lo < hi && (!FR || lvk <= (uint32_t)A.k)) {
             // first e >= lo with (e - rs) % S == s
             const int e0 = lo + (((s - (lo - rs)) % S) + S) % S;
             for (int e = e0; e < hi; e += kUnroll * S) {
@@ -414,8 +402,6 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
                     for (int i = 0; i < VEC; ++i) sx.v[i] = fmaf(w[u], x[u].v[i], sx.v[i]);
                 }
             }
-            if (push)
-                for (int e = e0; e < hi; e += S) frontier_push<RPB>(A, stage[e - cb].x);
         }
         __syncthreads();
     }

@@ -466,6 +466,7 @@ void set_frontier(gs_plan_s& P, int enable) {
         P.lev_nu.alloc(nr);
         P.blk_mu.alloc(nb);
         P.blk_nu.alloc(nb);
+        P.lev_flags.alloc(GS_MAX_K + 1);
     }
 }
 
@@ -475,13 +476,12 @@ namespace {
 // solves of the Euler kernel have no step index to compare a level with).
 bool frontier_on(const gs_plan_s& P) { return P.frontier && P.kernel != GS_KERNEL_EULER; }
 
-// Frontier levels of supp(h) (rows where any of the B columns is nonzero)
-// before step 1, with row blocks of the plan's launch shape; the steps of an
-// application advance them (an application from the same support finds them
-// already advanced, which changes nothing).
+// Hop levels of supp(h) (rows where any of the B columns is nonzero), exact up
+// to K hops, with row blocks of the plan's launch shape.
 void enqueue_levels(gs_plan_s& P, const float* h, Levels lev, hipStream_t st) {
     const int rpb = 4 * (64 / (P.shape.S * P.shape.C));
-    launch_support_levels(h, P.n, P.ldp, P.B, P.g->rowptr.p, P.g->col.p, rpb, lev.row, lev.blk, st);
+    launch_support_levels(h, P.n, P.ldp, P.B, P.g->rowptr.p, P.g->col.p, P.K, rpb, lev.row, lev.blk,
+                          P.lev_flags.p, st);
 }
 
 Levels levels_mu(gs_plan_s& P) { return {P.lev_mu.p, P.blk_mu.p}; }

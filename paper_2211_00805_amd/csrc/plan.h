@@ -18,11 +18,11 @@ struct StepSched {
     int cmask;
 };
 
-// Frontier levels of one support (rows, row blocks of the plan's shape);
+// Hop levels of one support (rows, row blocks of the plan's shape);
 // row == nullptr: dense steps.
 struct Levels {
-    uint8_t* row = nullptr;
-    uint8_t* blk = nullptr;
+    uint32_t* row = nullptr;
+    uint32_t* blk = nullptr;
 };
 
 struct ScaleEpi {
@@ -73,7 +73,8 @@ struct gs_plan_s {
     // frontier-sparse steps (opt-in): per-row hop levels of the supports the
     // applications start from (mu's also serves gs_heat_apply's X)
     int frontier = 0;
-    gs::DevBuf<uint8_t> lev_mu, lev_nu, blk_mu, blk_nu;
+    gs::DevBuf<uint32_t> lev_mu, lev_nu, blk_mu, blk_nu;
+    gs::DevBuf<int32_t> lev_flags;   // per-sweep flags of the level computation
 
     std::map<std::string, hipGraphExec_t> graphs;
     std::map<std::string, hipGraph_t> graph_defs;

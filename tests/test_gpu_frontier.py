@@ -303,3 +303,27 @@ def test_frontier_second_sinkhorn_call_and_barycenter(gs, curve):
             for p, bb in ((dense, bary[0]), (plan, bary[1]))]
     assert same_bits(bary[0], bary[1])
     assert np.array_equal(outs[0]["marg_err"], outs[1]["marg_err"])
+
+
+def test_frontier_sinkhorn_iteration_counts_share_a_plan(gs, curve):
+    """J = 1, 2, 5, 1, 3 on one plan: the first application from each support
+    advances its levels (at J = 1 that is the marginal check's), the captured
+    graphs of one count never serve another wrongly."""
+    n, labels, arrs, L = curve
+    K, t, B = 10, 1.0, 4
+    lam = lam_hat_of(L)
+    rng = np.random.default_rng(12)
+    pairs = [synth.cluster_block_pair(labels, s, 2, 1.0, rng) for s in (0, 2, 4, 6)]
+    mu = to_dev(np.stack([p[0] for p in pairs], axis=1))
+    nu = to_dev(np.stack([p[1] for p in pairs], axis=1))
+    g = gs.gs_graph_from_csr(n, *arrs)
+    dense = gs.Plan(g, K, B)
+    plan = gs.Plan(g, K, B)
+    plan.set_frontier(1)
+    for J in (1, 2, 5, 1, 3):
+        vw = [[torch.empty(n * B, device="cuda") for _ in range(2)] for _ in range(2)]
+        o = [gs.gs_sinkhorn(p, lam, t, mu, nu, J, v=x[0], w=x[1], want_marg=True)
+             for p, x in ((dense, vw[0]), (plan, vw[1]))]
+        assert np.array_equal(o[0]["dist"], o[1]["dist"]), J
+        assert np.array_equal(o[0]["marg_err"], o[1]["marg_err"]), J
+        assert same_bits(vw[0][0], vw[1][0]) and same_bits(vw[0][1], vw[1][1]), J
