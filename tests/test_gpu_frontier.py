@@ -8,9 +8,12 @@ signs of zeros count too), and compares them with the float64 oracle: heat
 applications from localised supports (single nodes on a path and a cycle,
 a few nodes on a banded graph with hub rows; K = 1..4, 20, 256; B = 1, 3, 32;
 both polynomial kernels; every launch shape; the time derivative; two calls
-with different supports on one plan), Algorithm 1 with and without vertex
-weights, with checkpoints and with records and the reverse sweep from them,
-and a barycenter on a plan whose Sinkhorn calls ran with the option.
+with different supports on one plan; all-zero and full supports, a graph
+smaller than one row block), Algorithm 1 with and without vertex weights
+(some of them zero), with checkpoints and with records and the reverse sweep
+from them, iteration counts 1, 2, 5, 1, 3 on one plan, a barycenter on a plan
+whose Sinkhorn calls ran with the option, and the backward-Euler kernel,
+which ignores it.
 """
 import numpy as np
 import pytest
@@ -327,3 +330,63 @@ def test_frontier_sinkhorn_iteration_counts_share_a_plan(gs, curve):
         assert np.array_equal(o[0]["dist"], o[1]["dist"]), J
         assert np.array_equal(o[0]["marg_err"], o[1]["marg_err"]), J
         assert same_bits(vw[0][0], vw[1][0]) and same_bits(vw[0][1], vw[1][1]), J
+
+
+def test_frontier_degenerate_supports(gs, graphs):
+    """An all-zero X (every row beyond every step: the result is exactly zero),
+    an all-zero column beside a one-node one, a single row block's worth of
+    graph (n below the rows of one block) and a support covering every row."""
+    n, arrs, L = graphs["band"]
+    K, t = 7, 1.0
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = g.edge_bound
+    plan = gs.Plan(g, K, 4)
+    X = np.zeros((n, 4), dtype=np.float32)
+    out = apply_both(gs, plan, lam, t, X)
+    assert same_bits(out[0][0], out[1][0]) and np.all(to_host(out[1][0]) == 0.0)
+    X[123, 1] = 1.0
+    out = apply_both(gs, plan, lam, t, X)
+    assert same_bits(out[0][0], out[1][0])
+    X[:] = np.random.default_rng(4).uniform(0.1, 1.0, X.shape)
+    out = apply_both(gs, plan, lam, t, X)
+    assert same_bits(out[0][0], out[1][0])
+
+    m = 10   # fewer rows than one block of any launch shape
+    gsm = gs.gs_graph_from_csr(m, *synth.cycle_graph(m))
+    small = gs.Plan(gsm, 3, 1)
+    x = np.zeros((m, 1), dtype=np.float32)
+    x[2, 0] = 1.0
+    out = apply_both(gs, small, 4.0, t, x)
+    assert same_bits(out[0][0], out[1][0])
+    ref = closed_forms.cycle_heat_apply(m, 4.0, t, 3, x.astype(np.float64))
+    assert np.abs(to_host(out[1][0]).reshape(m, 1) - ref).max() <= heat_tol(3, 1.0)
+
+
+def test_frontier_with_zero_vertex_weights(gs, curve):
+    """Vertex weights that vanish on part of the supports shrink supp(a w)
+    below supp(nu): the levels from supp(nu) stay a valid (looser) bound."""
+    n, labels, arrs, L = curve
+    K, t, J, B = 10, 1.0, 15, 4
+    rng = np.random.default_rng(21)
+    pairs = [synth.cluster_block_pair(labels, s, 2, 1.0, rng) for s in (0, 2, 4, 6)]
+    mu = np.stack([p[0] for p in pairs], axis=1).astype(np.float32)
+    nu = np.stack([p[1] for p in pairs], axis=1).astype(np.float32)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    a[rng.choice(n, n // 3, replace=False)] = 0.0
+    lam = lam_hat_of(L)
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, K, B)
+    sinkhorn_both(gs, plan, lam, t, mu, nu, J, a=a)
+
+
+def test_frontier_option_leaves_the_euler_kernel_alone(gs, graphs):
+    """The backward-Euler kernel ignores the option: the same results with it on."""
+    n, arrs, L = graphs["band"]
+    g = gs.gs_graph_from_csr(n, *arrs)
+    lam = g.edge_bound
+    X = local_columns(n, 4, np.random.default_rng(2))
+    plan = gs.Plan(g, 12, 4)
+    plan.set_kernel(gs.GS_KERNEL_EULER, 4, 0)
+    out = apply_both(gs, plan, lam, 0.5, X)
+    assert same_bits(out[0][0], out[1][0])
+    assert "kernel=euler" in plan.describe()
