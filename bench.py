@@ -81,9 +81,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the barycenter / plain-forward / Swiss-roll timings")
-    p.add_argument("--study", choices=["orders", "footprint", "frontier"], default=None,
+    p.add_argument("--study", choices=["orders", "footprint", "frontier", "reuse"], default=None,
                    help="instead of the benchmark: the step kernel and its gathers under several node orders, "
-                        "or the gather rate against the operand's footprint")
+                        "the gather rate against the operand's footprint, frontier-sparse steps on and off, "
+                        "or the gather reuse an on-chip tile could capture")
     p.add_argument("--probe-only", action="store_true",
                    help="set up the workload, then only time the fused step kernel and the copy kernel "
                         "(short run for profilers and counter collection)")
@@ -480,6 +481,46 @@ def permuted_csr(rp, col, w, order, np):
     return rp2.astype(np.int32), c2[o].astype(np.int32), w2[o].astype(np.float32)
 
 
+def reuse_study(args):
+    """How much gather reuse any on-chip tile could capture (one JSON line).
+
+    For parts of P consecutive rows of the 1M workload under four node orders,
+    the rows a part gathers from: distinct(neighbours) / nonzeros is the
+    share of the gathers that remain even if a cache or an LDS tile held
+    every row the part needs, and distinct x 128 B is the capacity that would
+    take (B = 32 float columns).  P = 16 is one block of the benchmark's
+    launch shape, 256 and 1024 what an LDS tile could cover, 32768 about one
+    4 MB L2 of 128-byte rows, 125000 one XCD's row range under the XCD-aware
+    block order.
+    """
+    import numpy as np
+
+    import paper_2211_00805_amd as gs
+    import synth
+
+    X, labels = synth.clusters_on_surface((10, 5), args.per_cluster, 100, 0.1, workload=5)
+    g0 = gs.gs_graph_from_points(X, args.knn)
+    rp, col, w, _ = g0.export()
+    del g0
+    log("[study] computing node orders ...")
+    orders = node_orders(X, labels, rp, col, np)
+    del X
+    n, nnz = int(rp.shape[0] - 1), int(col.shape[0])
+    res = {"study": "gather reuse", "n": n, "nnz": nnz, "row_bytes": 128, "orders": {}}
+    for name in ("generator", "cluster_grid", "pca_bisect", "random"):
+        rp2, c2, _ = permuted_csr(rp, col, w, orders[name], np)
+        rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp2))
+        per = {}
+        for P in (16, 256, 1024, 32768, 125000):
+            distinct = int(np.unique((rows // P) * n + c2.astype(np.int64)).size)
+            nparts = (n + P - 1) // P
+            per[str(P)] = {"distinct_over_nnz": round(distinct / nnz, 4),
+                           "mean_working_set_kb": round(distinct / nparts * 128 / 1024, 1)}
+        res["orders"][name] = per
+        log(f"[study] {name}: {per}")
+    print(json.dumps(res), flush=True)
+
+
 def order_study(args):
     """The step kernel and its gathers alone under each node order of the 1M workload (one JSON line)."""
     import numpy as np
@@ -724,6 +765,9 @@ def main():
         return
     if args.study == "frontier":
         frontier_study(args)
+        return
+    if args.study == "reuse":
+        reuse_study(args)
         return
 
     import numpy as np
