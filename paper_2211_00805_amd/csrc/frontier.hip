@@ -19,7 +19,7 @@ namespace gs {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kLanesPerRow = 8;   // lanes sharing a row's nonzeros in a sweep
+constexpr int kLanesPerRow = 8;   // lanes sharing a frontier row's nonzeros in a sweep
 
 int blocks_for(int64_t count) {
     int64_t g = (count + kBlk - 1) / kBlk;
@@ -41,34 +41,45 @@ __global__ __launch_bounds__(kBlk) void support_init_kernel(const float* h, int6
     }
 }
 
-// Sweep s: kLanesPerRow lanes per row; the lanes of a row at level s - 1 walk
+// Sweep s: a thread per row finds the rows at level s - 1 among its block's
+// kBlk rows and lists them in LDS; then kLanesPerRow lanes per listed row walk
 // its nonzeros (each every kLanesPerRow-th, four loads in flight) and lower
-// neighbours still farther out to s.
+// neighbours still farther out to s.  The scan reads one level per row; only
+// the frontier's rows read their nonzeros.
 __global__ __launch_bounds__(kBlk) void level_sweep_kernel(const int32_t* rowptr, const int32_t* col, int64_t n,
                                                            uint32_t* level, int32_t* flags, int s) {
     if (flags[s - 1] == 0) return;   // the frontier is empty: every level is final
+    __shared__ int32_t listed[kBlk];
+    __shared__ int nlisted;
     const int sub = threadIdx.x % kLanesPerRow;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kBlk / kLanesPerRow);
     const uint32_t prev = (uint32_t)(s - 1), cur = (uint32_t)s;
     bool found = false;
-    for (int64_t i = blockIdx.x * (int64_t)(kBlk / kLanesPerRow) + threadIdx.x / kLanesPerRow; i < n;
-         i += rows_per_grid) {
-        if (level[i] != prev) continue;
-        const int e1 = rowptr[i + 1];
-        for (int e = rowptr[i] + sub; e < e1; e += 4 * kLanesPerRow) {
-            int j[4];
-            uint32_t l[4];
+    for (int64_t base = blockIdx.x * (int64_t)kBlk; base < n; base += (int64_t)gridDim.x * kBlk) {
+        if (threadIdx.x == 0) nlisted = 0;
+        __syncthreads();
+        const int64_t i = base + threadIdx.x;
+        if (i < n && level[i] == prev) listed[atomicAdd(&nlisted, 1)] = (int32_t)i;
+        __syncthreads();
+        const int m = nlisted;
+        for (int r = threadIdx.x / kLanesPerRow; r < m; r += kBlk / kLanesPerRow) {
+            const int row = listed[r];
+            const int e1 = rowptr[row + 1];
+            for (int e = rowptr[row] + sub; e < e1; e += 4 * kLanesPerRow) {
+                int j[4];
+                uint32_t l[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) j[u] = e + u * kLanesPerRow < e1 ? col[e + u * kLanesPerRow] : -1;
+                for (int u = 0; u < 4; ++u) j[u] = e + u * kLanesPerRow < e1 ? col[e + u * kLanesPerRow] : -1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) l[u] = j[u] >= 0 ? level[j[u]] : 0u;
+                for (int u = 0; u < 4; ++u) l[u] = j[u] >= 0 ? level[j[u]] : 0u;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (l[u] > cur) {
-                    level[j[u]] = cur;
-                    found = true;
-                }
+                for (int u = 0; u < 4; ++u)
+                    if (l[u] > cur) {
+                        level[j[u]] = cur;
+                        found = true;
+                    }
+            }
         }
+        __syncthreads();   // the list is rebuilt by the next pass
     }
     if (found) flags[s] = 1;
 }
@@ -94,8 +105,8 @@ void launch_support_levels(const float* h, int64_t n, int ldp, int B, const int3
     hipLaunchKernelGGL(support_init_kernel, dim3(blocks_for(n > depth + 1 ? n : depth + 1)), dim3(kBlk), 0, st, h,
                        n, ldp, B, level, flags, depth);
     for (int s = 1; s <= depth; ++s)
-        hipLaunchKernelGGL(level_sweep_kernel, dim3(blocks_for(n * kLanesPerRow)), dim3(kBlk), 0, st, rowptr, col, n,
-                           level, flags, s);
+        hipLaunchKernelGGL(level_sweep_kernel, dim3(blocks_for(n)), dim3(kBlk), 0, st, rowptr, col, n, level, flags,
+                           s);
     hipLaunchKernelGGL(block_level_kernel, dim3(blocks_for((n + rpb - 1) / rpb)), dim3(kBlk), 0, st, level, n, rpb,
                        blk_level);
 }
