@@ -27,7 +27,8 @@ int blocks_for(int64_t count) {
     return (int)(g < 1 ? 1 : g);
 }
 
-// Level 0 where any of the B columns of h is nonzero, kFarLevel elsewhere;
+// Level 0 where any of the B columns of h is nonzero, kFarLevel elsewhere
+// (h: n x ldp with zero padding columns, as the plan's buffers hold it);
 // flags[s] (s = 0..depth) records whether sweep s found a new row (flags[0]:
 // the support itself, taken as nonempty).
 __global__ __launch_bounds__(kBlk) void support_init_kernel(const float* h, int64_t n, int ldp, int B,
@@ -35,8 +36,17 @@ __global__ __launch_bounds__(kBlk) void support_init_kernel(const float* h, int6
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t0 <= depth) flags[t0] = t0 == 0 ? 1 : 0;
     for (int64_t i = t0; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float* hr = h + i * ldp;
         bool in = false;
-        for (int c = 0; c < B; ++c) in = in || h[i * ldp + c] != 0.f;
+        if (ldp % 4 == 0) {   // padded rows of float4 groups (padding columns hold zeros)
+            const float4* h4 = reinterpret_cast<const float4*>(hr);
+            for (int c = 0; c < ldp / 4 && !in; ++c) {
+                const float4 v = h4[c];
+                in = v.x != 0.f || v.y != 0.f || v.z != 0.f || v.w != 0.f;
+            }
+        } else {
+            for (int c = 0; c < B && !in; ++c) in = hr[c] != 0.f;
+        }
         level[i] = in ? 0u : kFarLevel;
     }
 }
