@@ -390,3 +390,18 @@ def test_frontier_option_leaves_the_euler_kernel_alone(gs, graphs):
     out = apply_both(gs, plan, lam, 0.5, X)
     assert same_bits(out[0][0], out[1][0])
     assert "kernel=euler" in plan.describe()
+
+
+def test_frontier_setter_rejects_other_values(gs, graphs):
+    from paper_2211_00805_amd import _lib
+    n, arrs, L = graphs["band"]
+    g = gs.gs_graph_from_csr(n, *arrs)
+    plan = gs.Plan(g, 5, 1)
+    for bad in (2, -1):
+        with pytest.raises(gs.GeoSinkError, match="enable must be 0 or 1"):
+            _lib.check("gs_plan_set_frontier", _lib.lib.gs_plan_set_frontier(plan.handle, bad))
+    assert "frontier=on" not in plan.describe()
+    plan.set_frontier(True)
+    assert "frontier=on" in plan.describe()
+    plan.set_frontier(False)
+    assert "frontier=on" not in plan.describe()
