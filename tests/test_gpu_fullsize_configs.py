@@ -105,7 +105,8 @@ def support_l1(got_full, ref_on_supp, supp):
 
 def test_curve_100k_three_times(gs):
     """n = 100k cluster curve, one pair, K = 30, J = 500, t in {0.5, 2, 8} (the plain forward workload),
-    through the accumulating and the Clenshaw step forms."""
+    through the accumulating and the Clenshaw step forms, and the accumulating form with frontier-sparse
+    steps (bitwise the dense run's distance and scalings)."""
     rec, arr = load("curve")
     X, labels, mu, nu = synth.curve_pair_workload()
     assert synth.sha256(X) == rec["points_sha256"] and synth.sha256(mu) == rec["mu_sha256"]
@@ -118,13 +119,21 @@ def test_curve_100k_three_times(gs):
     supp = np.nonzero(mu > 0)[0]
     v = torch.empty(n, device="cuda")
     w = torch.empty(n, device="cuda")
-    for kernel in (gs.GS_KERNEL_CHEBYSHEV, gs.GS_KERNEL_CLENSHAW):   # the same polynomial, two recurrences
-        plan.set_kernel(kernel)
+    dense = {}
+    for kernel, frontier in ((gs.GS_KERNEL_CHEBYSHEV, 0), (gs.GS_KERNEL_CLENSHAW, 0), (gs.GS_KERNEL_CHEBYSHEV, 1)):
+        plan.set_kernel(kernel)   # the same polynomial, two recurrences
+        plan.set_frontier(frontier)
         for run in rec["runs"]:
             t = run["t"]
             out = gs.gs_sinkhorn(plan, lam, t, to_dev(mu), to_dev(nu), J, v=v, w=w, want_marg=True,
                                  want_floors=True)
             D = float(out["dist"][0])
+            bits = (out["dist"].view(np.int64).copy(), v.view(torch.int32).cpu(), w.view(torch.int32).cpu())
+            if kernel == gs.GS_KERNEL_CHEBYSHEV and not frontier:
+                dense[t] = bits
+            elif frontier:
+                assert np.array_equal(bits[0], dense[t][0]), t
+                assert torch.equal(bits[1], dense[t][1]) and torch.equal(bits[2], dense[t][2]), t
             r = osk.row_marginal(L, lam, t, K, to_host(v), to_host(w))[:, 0]
             l1 = support_l1(r, arr[f"row_t{t}"], supp)
             print(f"t={t}: D {D:.9f} oracle {run['D']:.9f} (rel {abs(D - run['D']) / abs(run['D']):.1e}); "
