@@ -105,7 +105,23 @@ __global__ __launch_bounds__(kBlk) void block_level_kernel(const uint32_t* level
     }
 }
 
+// Zeros in up to four float buffers of `count` elements each, one launch.
+__global__ __launch_bounds__(kBlk) void zero_buffers_kernel(float* b0, float* b1, float* b2, float* b3,
+                                                            int64_t count) {
+    float* bufs[4] = {b0, b1, b2, b3};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (bufs[q]) bufs[q][i] = 0.f;
+    }
+}
+
 }  // namespace
+
+void launch_zero_buffers(float* b0, float* b1, float* b2, float* b3, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(zero_buffers_kernel, dim3(blocks_for(count)), dim3(kBlk), 0, st, b0, b1, b2, b3, count);
+}
 
 void launch_support_levels(const float* h, int64_t n, int ldp, int B, const int32_t* rowptr, const int32_t* col,
                            int depth, int rpb, uint32_t* level, uint32_t* blk_level, int32_t* flags, hipStream_t st) {

@@ -117,6 +117,11 @@ struct StepArgs {
     // dense kernel's operands.
     const uint32_t* level;
     const uint32_t* blk_level;
+    // frontier, accumulating forms: the application zeroed its T and
+    // accumulator buffers before step 1, and this step is not the last; a
+    // block beyond the frontier then leaves at once (the dense kernel would
+    // write +0 there, which the buffers already hold)
+    int32_t skip_dead;
 };
 
 struct LaunchShape {
@@ -210,6 +215,8 @@ void launch_scale_epilogue(const float* acc, const float* num, float* out, float
 // exact up to `depth`, kFarLevel beyond; blk_level[b] = min level over rows
 // [b rpb, (b + 1) rpb); flags: depth + 1 ints of scratch
 constexpr uint32_t kFarLevel = 1u << 30;
+// zeros in up to four float buffers (nullptr: none) of count elements each
+void launch_zero_buffers(float* b0, float* b1, float* b2, float* b3, int64_t count, hipStream_t st);
 void launch_support_levels(const float* h, int64_t n, int ldp, int B, const int32_t* rowptr, const int32_t* col,
                            int depth, int rpb, uint32_t* level, uint32_t* blk_level, int32_t* flags, hipStream_t st);
 

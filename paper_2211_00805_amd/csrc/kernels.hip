@@ -235,10 +235,15 @@ __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off,
 
 // Frontier rows (level above the step index) have all-zero operands: they
 // skip their gathers, whole blocks of them their CSR, and they still load
-// their own operands (issued before any level is known, which keeps the
+// their own operands (issued before any row level is known, which keeps the
 // level loads off the blocks' critical path).  The epilogue then computes
 // from the same operands as the dense kernel with zero neighbour sums, which
-// gives the dense kernel's bits, signs of zeros included.
+// gives the dense kernel's bits, signs of zeros included.  In the
+// accumulating forms those bits are +0 for T_k and the accumulator, so when
+// the application has zeroed its buffers beforehand (A.skip_dead, never on
+// the last step, whose epilogue writes every row) a whole block beyond the
+// frontier returns before loading anything.  Clenshaw's recurrence can give
+// -0 there and always takes the full path.
 
 // Rows with more than A.long_thr nonzeros: one block per row and column tile,
 // 256/C lanes splitting the nonzeros, a block reduction through LDS.  FR: the
@@ -260,6 +265,7 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
     if (s == 0 && colok) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
     const bool dead = FR && A.level[row] > (uint32_t)A.k;   // block-uniform
+    if (FR && MODE != kModeClen && A.skip_dead && dead) return;
     const int rs = A.rowptr[row], re = (colok && !dead) ? A.rowptr[row + 1] : rs;
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
@@ -325,6 +331,9 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int L = A.remap ? xcd_remap(bt, (int)gridDim.x - nlb) : bt;
     const int rt = L / ncoltiles;
     const int ct = L - rt * ncoltiles;
+    if constexpr (FR && MODE != kModeClen) {
+        if (A.skip_dead && A.blk_level[rt] > (uint32_t)A.k) return;   // zeros already in place
+    }
     const int lr = lane % LPR;
     const int s = lr / C;
     const int c = lr - s * C;

@@ -355,10 +355,17 @@ void enqueue_cheb_apply(gs_plan_s& P, const float* X, ApplyMode mode, const Scal
     StepArgs base = base_args(P);
     base.level = lev.row;
     base.blk_level = lev.blk;
+    if (lev.row) {
+        // frontier: zeros in the T and accumulator buffers let blocks beyond
+        // the frontier leave at once on every step but the last
+        launch_zero_buffers(P.U.p, P.V.p, P.ACC.p, mode == ApplyMode::Dual ? P.ACC2.p : nullptr, (int64_t)P.sz(),
+                            st);
+    }
     const std::vector<StepSched> sched = step_schedule(P.K, mode);
     for (int k = 1; k <= P.K; ++k) {
         StepArgs a = base;
         a.k = k;
+        a.skip_dead = lev.row && k < P.K && !(sched[k - 1].flags & STEP_EPI_SCALE) ? 1 : 0;
         a.tprev = k == 1 ? X : T(P, k - 1);
         a.tprev2 = k >= 2 ? (k == 2 ? X : T(P, k - 2)) : nullptr;
         a.tout = T(P, k);
