@@ -320,6 +320,34 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
                         const double* alpha, int32_t iters, float phi, float* bary, float* v,
                         float* w, double* marg_err, int64_t* n_floored, hipStream_t stream);
 
+/* Graph-level forms of the four calls above (the heat application of Sec.
+ * "Chebyshev Polynomials", Algorithm 1, its reverse sweep and the barycenter
+ * problem of Sec. "Interpolation with discrete support"), taking the graph, K and
+ * the number of columns (B pairs, or m input distributions) directly.  The
+ * arguments that follow mean what they mean for the plan-bound call, which
+ * runs them and whose validation and errors apply.  plan: NULL uses a plan
+ * the graph keeps for (K, B), created on the first such call with default
+ * flags (default launch shape, captured hipGraphs; no autotuning) and freed
+ * by gs_graph_destroy; or a plan created for this graph, K and B
+ * (GS_ERR_INVALID otherwise).  Calls sharing a plan share its workspace:
+ * calls on one graph with the same K and B and plan NULL must not overlap
+ * (another host thread or stream); give each its own plan instead. */
+gs_status gs_graph_heat_apply(gs_graph g, double lambda_hat, double t, int32_t K, const float* X,
+                              float* Y, float* Ydt, int32_t B, gs_plan plan, hipStream_t stream);
+gs_status gs_graph_sinkhorn(gs_graph g, double lambda_hat, double t, int32_t K, const float* a,
+                            const float* mu, const float* nu, int32_t B, int32_t iters, float phi,
+                            int32_t ckpt_every, float* ckpt, float* v, float* w, double* dist,
+                            double* marg_err, int64_t* n_floored, gs_plan plan, hipStream_t stream);
+gs_status gs_graph_sinkhorn_backward(gs_graph g, double lambda_hat, double t, int32_t K,
+                                     const float* a, const float* mu, const float* nu, int32_t B,
+                                     int32_t iters, float phi, int32_t ckpt_every, const float* ckpt,
+                                     const double* grad_dist, float* grad_mu, float* grad_nu,
+                                     double* grad_t, gs_plan plan, hipStream_t stream);
+gs_status gs_graph_barycenter(gs_graph g, double lambda_hat, double t, int32_t K, const float* a,
+                              const float* mus, const double* alpha, int32_t m, int32_t iters,
+                              float phi, float* bary, float* v, float* w, double* marg_err,
+                              int64_t* n_floored, gs_plan plan, hipStream_t stream);
+
 /* Expectation of node features under a (not necessarily normalised) signal:
  * out[c] = sum_i p_i Y[i*d + c] / sum_i p_i, c < d (float64 sums, two
  * deterministic passes).  The Expected Barycenter Effect (Sec. "Geodesic

@@ -12,6 +12,7 @@ _API = ("Graph", "Plan", "GeoSinkError", "GS_PLAN_AUTOTUNE", "GS_PLAN_NO_GRAPH",
         "GS_KERNEL_EULER", "GS_RECORD_ALL", "ckpt_floats", "gs_abi_version",
         "gs_graph_from_points", "gs_graph_from_csr", "gs_lambda_max", "gs_cheby_coeffs", "gs_cheby_tail_bound",
         "gs_plan_create", "gs_heat_apply", "gs_heat_apply_noalloc", "gs_sinkhorn", "gs_sinkhorn_backward", "gs_barycenter",
+        "gs_graph_heat_apply", "gs_graph_sinkhorn", "gs_graph_sinkhorn_backward", "gs_graph_barycenter",
         "gs_expectation", "gs_gather_columns", "gs_accumulate_columns", "gs_plan_time_step", "gs_stream_copy", "gs_stream_gather", "current_stream", "n_checkpoints")
 _AUTOGRAD = ("GeoSinkhornDistance", "geodesic_sinkhorn_distance")
 _FAMILIES = ("family_barycenter", "barycentric_distance", "expected_barycenter_effect")

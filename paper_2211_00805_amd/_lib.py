@@ -72,6 +72,16 @@ _SIGS = {
                                        C.c_int32, P_f32, P_f64, P_f32, P_f32, P_f64, c_stream]),
     "gs_barycenter": (C.c_int, [c_plan, C.c_double, C.c_double, P_f32, P_f32, P_f64, C.c_int32, C.c_float,
                                 P_f32, P_f32, P_f32, P_f64, P_i64, c_stream]),
+    "gs_graph_heat_apply": (C.c_int, [c_graph, C.c_double, C.c_double, C.c_int32, P_f32, P_f32, P_f32, C.c_int32,
+                                      c_plan, c_stream]),
+    "gs_graph_sinkhorn": (C.c_int, [c_graph, C.c_double, C.c_double, C.c_int32, P_f32, P_f32, P_f32, C.c_int32,
+                                    C.c_int32, C.c_float, C.c_int32, P_f32, P_f32, P_f32, P_f64, P_f64, P_i64, c_plan,
+                                    c_stream]),
+    "gs_graph_sinkhorn_backward": (C.c_int, [c_graph, C.c_double, C.c_double, C.c_int32, P_f32, P_f32, P_f32,
+                                             C.c_int32, C.c_int32, C.c_float, C.c_int32, P_f32, P_f64, P_f32, P_f32,
+                                             P_f64, c_plan, c_stream]),
+    "gs_graph_barycenter": (C.c_int, [c_graph, C.c_double, C.c_double, C.c_int32, P_f32, P_f32, P_f64, C.c_int32,
+                                      C.c_int32, C.c_float, P_f32, P_f32, P_f32, P_f64, P_i64, c_plan, c_stream]),
     "gs_expectation": (C.c_int, [P_f32, P_f32, C.c_int64, C.c_int32, c_stream, P_f64]),
     "gs_plan_time_step": (C.c_int, [c_plan, C.c_int32, c_stream, P_f64, P_f64]),
     "gs_stream_copy": (C.c_int, [P_f32, P_f32, C.c_int64, c_stream]),

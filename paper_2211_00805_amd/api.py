@@ -290,6 +290,88 @@ def gs_barycenter(plan: Plan, lambda_hat: float, t: float, mus: torch.Tensor, al
     return {"marg_err": marg if want_marg else None, "n_floored": nfl.value if want_floors else None}
 
 
+# ----------------------------------------------------------------------------- graph-level forms
+
+def _cols(graph: Graph, x: torch.Tensor, name: str) -> int:
+    """Columns of an n x B (or n,) device array on the graph's nodes."""
+    if x.numel() % graph.n != 0 or x.numel() == 0:
+        raise ValueError(f"{name} must hold n x B floats (n = {graph.n})")
+    return x.numel() // graph.n
+
+
+def _plan_handle(plan: Plan | None):
+    return None if plan is None else plan.handle
+
+
+def gs_graph_heat_apply(graph: Graph, lambda_hat: float, t: float, K: int, X: torch.Tensor, Y: torch.Tensor,
+                        Ydt: torch.Tensor | None = None, plan: Plan | None = None) -> None:
+    """gs_graph_heat_apply: Y = p_K(L, t) X on the graph (B from X's size); plan None: the graph's own."""
+    B = _cols(graph, X, "X")
+    nb = graph.n * B
+    check("gs_graph_heat_apply", lib.gs_graph_heat_apply(
+        graph.handle, float(lambda_hat), float(t), int(K), _dev(X, "X", nb), _dev(Y, "Y", nb), _dev(Ydt, "Ydt", nb),
+        int(B), _plan_handle(plan), current_stream()))
+
+
+def gs_graph_sinkhorn(graph: Graph, lambda_hat: float, t: float, K: int, mu: torch.Tensor, nu: torch.Tensor,
+                      iters: int, phi: float = 1e-30, a: torch.Tensor | None = None, ckpt_every: int = 0,
+                      ckpt: torch.Tensor | None = None, v: torch.Tensor | None = None, w: torch.Tensor | None = None,
+                      want_dist: bool = True, want_marg: bool = False, want_floors: bool = False,
+                      plan: Plan | None = None):
+    """gs_graph_sinkhorn: Algorithm 1 for the B pairs (B from mu's size); returns dict(dist, marg_err, n_floored)."""
+    B = _cols(graph, mu, "mu")
+    nb = graph.n * B
+    dist = np.zeros(B, dtype=np.float64)
+    marg = np.zeros(B, dtype=np.float64)
+    nfl = C.c_int64(0)
+    check("gs_graph_sinkhorn", lib.gs_graph_sinkhorn(
+        graph.handle, float(lambda_hat), float(t), int(K), _dev(a, "a", graph.n), _dev(mu, "mu", nb),
+        _dev(nu, "nu", nb), int(B), int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"), _dev(v, "v", nb),
+        _dev(w, "w", nb), dist.ctypes.data_as(_lib.P_f64) if want_dist else None,
+        marg.ctypes.data_as(_lib.P_f64) if want_marg else None, C.byref(nfl) if want_floors else None,
+        _plan_handle(plan), current_stream()))
+    return {"dist": dist if want_dist else None, "marg_err": marg if want_marg else None,
+            "n_floored": nfl.value if want_floors else None}
+
+
+def gs_graph_sinkhorn_backward(graph: Graph, lambda_hat: float, t: float, K: int, mu: torch.Tensor,
+                               nu: torch.Tensor, iters: int, ckpt_every: int, ckpt: torch.Tensor, grad_dist,
+                               phi: float = 1e-30, a: torch.Tensor | None = None,
+                               grad_mu: torch.Tensor | None = None, grad_nu: torch.Tensor | None = None,
+                               want_grad_t: bool = True, plan: Plan | None = None):
+    """gs_graph_sinkhorn_backward: the reverse sweep; returns the per-pair gradient in t (host) or None."""
+    B = _cols(graph, mu, "mu")
+    nb = graph.n * B
+    gd = np.ascontiguousarray(np.broadcast_to(np.asarray(grad_dist, dtype=np.float64), (B,)))
+    gt = np.zeros(B, dtype=np.float64)
+    check("gs_graph_sinkhorn_backward", lib.gs_graph_sinkhorn_backward(
+        graph.handle, float(lambda_hat), float(t), int(K), _dev(a, "a", graph.n), _dev(mu, "mu", nb),
+        _dev(nu, "nu", nb), int(B), int(iters), float(phi), int(ckpt_every), _dev(ckpt, "ckpt"),
+        gd.ctypes.data_as(_lib.P_f64), _dev(grad_mu, "grad_mu", nb), _dev(grad_nu, "grad_nu", nb),
+        gt.ctypes.data_as(_lib.P_f64) if want_grad_t else None, _plan_handle(plan), current_stream()))
+    return gt if want_grad_t else None
+
+
+def gs_graph_barycenter(graph: Graph, lambda_hat: float, t: float, K: int, mus: torch.Tensor, alpha, iters: int,
+                        bary: torch.Tensor, phi: float = 1e-30, a: torch.Tensor | None = None,
+                        v: torch.Tensor | None = None, w: torch.Tensor | None = None, want_marg: bool = False,
+                        want_floors: bool = False, plan: Plan | None = None):
+    """gs_graph_barycenter: the barycenter of the m columns of mus (m from its size)."""
+    m = _cols(graph, mus, "mus")
+    nb = graph.n * m
+    al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+    if al.shape != (m,):
+        raise ValueError("alpha must have m entries")
+    marg = np.zeros(m, dtype=np.float64)
+    nfl = C.c_int64(0)
+    check("gs_graph_barycenter", lib.gs_graph_barycenter(
+        graph.handle, float(lambda_hat), float(t), int(K), _dev(a, "a", graph.n), _dev(mus, "mus", nb),
+        al.ctypes.data_as(_lib.P_f64), int(m), int(iters), float(phi), _dev(bary, "bary", graph.n),
+        _dev(v, "v", nb), _dev(w, "w", nb), marg.ctypes.data_as(_lib.P_f64) if want_marg else None,
+        C.byref(nfl) if want_floors else None, _plan_handle(plan), current_stream()))
+    return {"marg_err": marg if want_marg else None, "n_floored": nfl.value if want_floors else None}
+
+
 def gs_expectation(p: torch.Tensor, Y: torch.Tensor) -> np.ndarray:
     """sum_i p_i Y[i, :] / sum_i p_i for device p (n,) and Y (n, d) (or (n,))."""
     n = p.numel()

@@ -60,6 +60,26 @@ void require_device() {
         fail(GS_ERR_NO_DEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
 }
 
+// The plan a graph-level call runs on: the caller's, which must belong to
+// (g, K, B), or the one the graph keeps for (K, B), created on first use
+// with default flags (default launch shape, captured graphs).
+gs_plan resolve_plan(gs_graph g, int32_t K, int32_t B, gs_plan plan) {
+    GS_REQUIRE(g != nullptr, "graph is NULL");
+    GS_REQUIRE(K >= 1 && K <= GS_MAX_K, "K must be in [1, GS_MAX_K]");
+    GS_REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+    if (plan) {
+        GS_REQUIRE(plan->g == g && plan->K == K && plan->B == B, "plan was created for another graph, K or B");
+        return plan;
+    }
+    std::lock_guard<std::mutex> lk(g->plans_mu);
+    gs_plan& slot = g->plans[{K, B}];
+    if (!slot) {
+        require_device();
+        slot = plan_create(g, K, B, 0, nullptr);
+    }
+    return slot;
+}
+
 void check_plan_args(gs_plan p, double lam, double t) {
     GS_REQUIRE(p != nullptr, "plan is NULL");
     GS_REQUIRE(std::isfinite(lam) && lam > 0.0, "lambda_hat must be finite and > 0");
@@ -137,7 +157,11 @@ gs_status gs_graph_export(gs_graph g, int32_t* rowptr, int32_t* col, float* w, f
     });
 }
 
-void gs_graph_destroy(gs_graph g) { delete g; }
+void gs_graph_destroy(gs_graph g) {
+    if (g)
+        for (auto& kv : g->plans) delete kv.second;
+    delete g;
+}
 
 gs_status gs_lambda_max(gs_graph g, int32_t iters, uint64_t seed, double safety, hipStream_t stream,
                         double* lambda_hat) {
@@ -325,6 +349,45 @@ gs_status gs_barycenter(gs_plan p, double lambda_hat, double t, const float* a, 
         for (int i = 0; i < p->B; ++i) GS_REQUIRE(std::isfinite(alpha[i]) && alpha[i] >= 0.0, "alpha must be >= 0");
         barycenter(*p, lambda_hat, t, a, mus, alpha, iters, phi, bary, v, w, marg_err, n_floored, stream);
     });
+}
+
+gs_status gs_graph_heat_apply(gs_graph g, double lambda_hat, double t, int32_t K, const float* X, float* Y,
+                              float* Ydt, int32_t B, gs_plan plan, hipStream_t stream) {
+    gs_plan p = nullptr;
+    const gs_status s = guarded([&] { p = resolve_plan(g, K, B, plan); });
+    return s != GS_OK ? s : gs_heat_apply(p, lambda_hat, t, X, Y, Ydt, stream);
+}
+
+gs_status gs_graph_sinkhorn(gs_graph g, double lambda_hat, double t, int32_t K, const float* a, const float* mu,
+                            const float* nu, int32_t B, int32_t iters, float phi, int32_t ckpt_every, float* ckpt,
+                            float* v, float* w, double* dist, double* marg_err, int64_t* n_floored, gs_plan plan,
+                            hipStream_t stream) {
+    gs_plan p = nullptr;
+    const gs_status s = guarded([&] { p = resolve_plan(g, K, B, plan); });
+    return s != GS_OK ? s
+                      : gs_sinkhorn(p, lambda_hat, t, a, mu, nu, iters, phi, ckpt_every, ckpt, v, w, dist, marg_err,
+                                    n_floored, stream);
+}
+
+gs_status gs_graph_sinkhorn_backward(gs_graph g, double lambda_hat, double t, int32_t K, const float* a,
+                                     const float* mu, const float* nu, int32_t B, int32_t iters, float phi,
+                                     int32_t ckpt_every, const float* ckpt, const double* grad_dist, float* grad_mu,
+                                     float* grad_nu, double* grad_t, gs_plan plan, hipStream_t stream) {
+    gs_plan p = nullptr;
+    const gs_status s = guarded([&] { p = resolve_plan(g, K, B, plan); });
+    return s != GS_OK ? s
+                      : gs_sinkhorn_backward(p, lambda_hat, t, a, mu, nu, iters, phi, ckpt_every, ckpt, grad_dist,
+                                             grad_mu, grad_nu, grad_t, stream);
+}
+
+gs_status gs_graph_barycenter(gs_graph g, double lambda_hat, double t, int32_t K, const float* a, const float* mus,
+                              const double* alpha, int32_t m, int32_t iters, float phi, float* bary, float* v,
+                              float* w, double* marg_err, int64_t* n_floored, gs_plan plan, hipStream_t stream) {
+    gs_plan p = nullptr;
+    const gs_status s = guarded([&] { p = resolve_plan(g, K, m, plan); });
+    return s != GS_OK ? s
+                      : gs_barycenter(p, lambda_hat, t, a, mus, alpha, iters, phi, bary, v, w, marg_err, n_floored,
+                                      stream);
 }
 
 gs_status gs_expectation(const float* p, const float* Y, int64_t n, int32_t d, hipStream_t stream, double* out) {

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/geosink.h"
@@ -252,4 +255,8 @@ struct gs_graph_s {
     std::vector<float> h_val, h_deg;
     int32_t n_components = 0;
     double deg_max = 0.0, edge_bound = 0.0, median = 0.0;
+    // plans the graph-level calls create for (K, B) when given none; freed
+    // with the graph
+    std::mutex plans_mu;
+    std::map<std::pair<int32_t, int32_t>, gs_plan_s*> plans;
 };

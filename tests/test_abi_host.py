@@ -101,6 +101,17 @@ def test_validation_rejects_before_any_device_call():
     assert b"plan is NULL" in lib.gs_last_error()
     assert lib.gs_plan_set_frontier(None, 1) == -1
     assert b"plan is NULL" in lib.gs_last_error()
+    assert lib.gs_graph_heat_apply(None, 2.0, 1.0, 10, None, None, None, 4, None, None) == -1
+    assert b"graph is NULL" in lib.gs_last_error()
+    assert lib.gs_graph_sinkhorn(None, 2.0, 1.0, 10, None, None, None, 4, 5, 1e-30, 0, None, None, None, None,
+                                 None, None, None, None) == -1
+    assert b"graph is NULL" in lib.gs_last_error()
+    assert lib.gs_graph_sinkhorn_backward(None, 2.0, 1.0, 10, None, None, None, 4, 5, 1e-30, 1, None, None, None,
+                                          None, None, None, None) == -1
+    assert b"graph is NULL" in lib.gs_last_error()
+    assert lib.gs_graph_barycenter(None, 2.0, 1.0, 10, None, None, None, 4, 5, 1e-30, None, None, None, None, None,
+                                   None, None) == -1
+    assert b"graph is NULL" in lib.gs_last_error()
     assert lib.gs_heat_apply_noalloc(None, 2.0, 1.0, 10, None, None, 4, None) == -1
     assert b"graph is NULL" in lib.gs_last_error()
 
