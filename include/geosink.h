@@ -183,9 +183,8 @@ gs_status gs_plan_set_csr_hint(gs_plan p, int32_t streamed);
  * from supp(mu) for the applications to a v and from supp(nu) for those to
  * a w after the first iteration (which applies to w = 1 densely).  Step k
  * then skips the gathers of rows more than k hops away, and a block of such
- * rows skips its CSR (in the accumulating form, on every step but the last,
- * it skips everything: each application zeroes its T and accumulator
- * buffers first).  Results are bitwise those of the dense steps.  The
+ * rows skips its CSR (on every step but the last it skips everything: each
+ * application zeroes its T and accumulator buffers first).  Results are bitwise those of the dense steps.  The
  * option pays where supports stay localised for many hops (a few nodes on
  * a large sparse graph) and costs the distance sweeps and about a
  * microsecond per step where they cover the graph within a few hops (kNN

@@ -120,10 +120,10 @@ struct StepArgs {
     // dense kernel's operands.
     const uint32_t* level;
     const uint32_t* blk_level;
-    // frontier, accumulating forms: the application zeroed its T and
-    // accumulator buffers before step 1, and this step is not the last; a
-    // block beyond the frontier then leaves at once (the dense kernel would
-    // write +0 there, which the buffers already hold)
+    // frontier: the application zeroed its T (u) and accumulator buffers
+    // before step 1, and this step is not the last; a block beyond the
+    // frontier then leaves at once (the dense kernel would write +0 there,
+    // which the buffers already hold)
     int32_t skip_dead;
 };
 

@@ -159,7 +159,9 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& A, int row, size_t
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const float yx = fmaf(alpha, fmaf(sw, own.v[i], -sx.v[i]), -own.v[i]);   // (y G)_i
-            t.v[i] = fmaf(cy, yx, fmaf(cx, ac.v[i], -p2.v[i]));                       // ac holds X
+            // ac holds X; adding +0 turns a -0 into +0 and changes no other value, so
+            // rows beyond the frontier hold +0 here as in the accumulating forms
+            t.v[i] = fmaf(cy, yx, fmaf(cx, ac.v[i], -p2.v[i])) + 0.f;
             accn.v[i] = t.v[i];
         }
     } else {
@@ -238,12 +240,12 @@ __device__ __forceinline__ void load_row_operands(const StepArgs& A, size_t off,
 // their own operands (issued before any row level is known, which keeps the
 // level loads off the blocks' critical path).  The epilogue then computes
 // from the same operands as the dense kernel with zero neighbour sums, which
-// gives the dense kernel's bits, signs of zeros included.  In the
-// accumulating forms those bits are +0 for T_k and the accumulator, so when
-// the application has zeroed its buffers beforehand (A.skip_dead, never on
-// the last step, whose epilogue writes every row) a whole block beyond the
-// frontier returns before loading anything.  Clenshaw's recurrence can give
-// -0 there and always takes the full path.
+// gives the dense kernel's bits, signs of zeros included.  Those bits are
+// +0 for T_k (u_k in Clenshaw's form, whose update adds +0 to turn -0 into
+// +0) and the accumulator, so when the application has zeroed its buffers
+// beforehand (A.skip_dead, never on the last step, whose epilogue writes
+// every row) a whole block beyond the frontier returns before loading
+// anything.
 
 // Rows with more than A.long_thr nonzeros: one block per row and column tile,
 // 256/C lanes splitting the nonzeros, a block reduction through LDS.  FR: the
@@ -265,7 +267,7 @@ __device__ __forceinline__ void long_row_block(const StepArgs& A, int item, int 
     Vec<VEC> own = vzero<VEC>(), p2 = vzero<VEC>(), ac = vzero<VEC>(), ac2 = vzero<VEC>();
     if (s == 0 && colok) load_row_operands<VEC, MODE>(A, off, own, p2, ac, ac2);
     const bool dead = FR && A.level[row] > (uint32_t)A.k;   // block-uniform
-    if (FR && MODE != kModeClen && A.skip_dead && dead) return;
+    if (FR && A.skip_dead && dead) return;
     const int rs = A.rowptr[row], re = (colok && !dead) ? A.rowptr[row + 1] : rs;
     const float* __restrict__ xcol = A.tprev + colofs;
     Vec<VEC> sx = vzero<VEC>();
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(StepArgs A) {
     const int L = A.remap ? xcd_remap(bt, (int)gridDim.x - nlb) : bt;
     const int rt = L / ncoltiles;
     const int ct = L - rt * ncoltiles;
-    if constexpr (FR && MODE != kModeClen) {
+    if constexpr (FR) {
         if (A.skip_dead && A.blk_level[rt] > (uint32_t)A.k) return;   // zeros already in place
     }
     const int lr = lane % LPR;

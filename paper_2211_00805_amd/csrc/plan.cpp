@@ -390,10 +390,12 @@ void enqueue_clenshaw_apply(gs_plan_s& P, const float* X, ApplyMode mode, const 
     StepArgs base = base_args(P);
     base.level = lev.row;
     base.blk_level = lev.blk;
+    if (lev.row) launch_zero_buffers(P.U.p, P.V.p, P.ACC.p, nullptr, (int64_t)P.sz(), st);   // as above
     const std::vector<StepSched> sched = clenshaw_schedule(P.K, mode);
     for (int j = 1; j <= P.K; ++j) {
         StepArgs a = base;
         a.k = j;
+        a.skip_dead = lev.row && j < P.K && !(sched[j - 1].flags & STEP_EPI_SCALE) ? 1 : 0;
         a.tprev = j == 1 ? X : T(P, j - 1);
         a.tprev2 = j >= 3 ? T(P, j - 2) : nullptr;
         a.tout = T(P, j);

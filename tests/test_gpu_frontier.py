@@ -169,16 +169,20 @@ def test_frontier_two_calls_move_the_support(gs, hubgraph):
         assert same_bits(Y0, Y1), seed
 
 
+@pytest.mark.parametrize("kernel", ["chebyshev", "clenshaw"])
 @pytest.mark.parametrize("K", [50, 256])
-def test_frontier_cycle_single_node(gs, K):
-    """One node on a cycle: the frontier grows one hop per step; K = 256 runs
-    past the largest level a byte holds (rows 255 hops out and farther keep
-    level 255 and are computed from step 255 on)."""
+def test_frontier_cycle_single_node(gs, K, kernel):
+    """One node on a cycle: the frontier grows one hop per step, so almost
+    every block leaves at once on every step but the last; K = 256 (the
+    largest degree) on a 2000-node cycle, where the frontier covers half the
+    rows by the last step."""
     n, t, lam = 100_000 if K == 50 else 2000, 2.0, 4.0
     g = gs.gs_graph_from_csr(n, *synth.cycle_graph(n))
     X = np.zeros((n, 1), dtype=np.float32)
     X[n // 3, 0] = 1.0
     plan = gs.Plan(g, K, 1)
+    if kernel == "clenshaw":
+        plan.set_kernel(gs.GS_KERNEL_CLENSHAW)
     out = apply_both(gs, plan, lam, t, X)
     assert same_bits(out[0][0], out[1][0])
     ref = closed_forms.cycle_heat_apply(n, lam, t, K, X.astype(np.float64))
