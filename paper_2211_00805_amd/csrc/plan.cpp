@@ -467,8 +467,8 @@ void enqueue_apply(gs_plan_s& P, const float* X, ApplyMode mode, const ScaleEpi&
 }
 
 void set_frontier(gs_plan_s& P, int enable) {
-    P.frontier = enable;
-    if (enable && !P.lev_mu.p) {
+    // the buffers first: a failed allocation leaves the option off
+    if (enable && !P.lev_flags.p) {
         const size_t nr = P.n ? (size_t)P.n : 1;
         const size_t nb = nr / 4 + 1;   // row blocks of the smallest shape (4 rows)
         P.lev_mu.alloc(nr);
@@ -477,6 +477,7 @@ void set_frontier(gs_plan_s& P, int enable) {
         P.blk_nu.alloc(nb);
         P.lev_flags.alloc(GS_MAX_K + 1);
     }
+    P.frontier = enable;
 }
 
 namespace {
